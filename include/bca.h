@@ -1,0 +1,200 @@
+/*
+ * bca.h -- C ABI of the MI355X Bi-cADMM library (libbca.so).
+ *
+ * Bi-cADMM (Olama, Lundell, Kronqvist, Ahmadi, Camponogara, "A GPU-Accelerated
+ * Bi-linear ADMM Algorithm for Distributed Sparse Machine Learning") solves the
+ * sparse machine-learning problem of Sec. 2,
+ *
+ *     min_x  sum_i l_i(A_i x; b_i) + ||x||^2 / (2 gamma)   s.t.  ||x||_0 <= kappa,
+ *
+ * over N sample partitions (the paper's computational nodes), each split into M
+ * feature blocks (the paper's GPUs of a node, Sec. 3.1).  On one GPU every
+ * partition and block lives in device memory and all of Algorithms 1 and 2 runs
+ * in this library's HIP kernels.
+ *
+ * Conventions
+ *   - Every function returns int: BCA_OK (0) or a negative BCA_E_* code; no
+ *     function throws across the ABI.  bca_last_error() gives a thread-local
+ *     message for the last failure on the calling thread.
+ *   - The caller owns every buffer it passes.  bca_set_data copies A and b into
+ *     library-owned device memory and keeps no caller pointer.  All device state
+ *     is owned by the problem handle and released by bca_destroy.
+ *   - All device work is enqueued on the HIP stream given to bca_create (NULL =
+ *     the null stream).  Functions that return host data synchronise that stream.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Vectors of length n x C are stored feature-major: element (k, c) at k*C + c.
+ */
+#ifndef BCA_H
+#define BCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bca_problem_s* bca_problem;
+
+/* Return codes. */
+enum {
+  BCA_OK = 0,
+  BCA_E_INVALID = -1,   /* bad argument or parameter */
+  BCA_E_OOM = -2,       /* device allocation failed */
+  BCA_E_STATE = -3,     /* call out of order (e.g. step before finalize) */
+  BCA_E_NONFINITE = -4, /* NaN/Inf in the data or in the iterates */
+  BCA_E_DEVICE = -5,    /* HIP runtime error */
+  BCA_E_BUDGET = -6,    /* request exceeds a memory budget */
+  BCA_E_NOTFOUND = -7,  /* unknown ticket or index */
+  BCA_E_CANCELLED = -8  /* request was cancelled */
+};
+
+/* Loss functions l_i (Sec. 2 lists sparse linear, logistic and softmax
+ * regression; the experimental section fixes the squared loss without 1/2):
+ *   SQUARED   l(q; b) = sum_k (q_k - b_k)^2,          b real
+ *   LOGISTIC  l(q; b) = sum_k log(1 + exp(-b_k q_k)),  b_k in {-1, +1}
+ *   SOFTMAX   l(Q; y) = sum_k LSE(Q_k) - Q_{k, y_k},   y_k in {0..C-1};
+ *             the sparsity then counts rows of the n x C coefficient matrix. */
+enum { BCA_LOSS_SQUARED = 0, BCA_LOSS_LOGISTIC = 1, BCA_LOSS_SOFTMAX = 2 };
+
+/* Storage precision of A.  F64: FP64 arithmetic throughout.  F32: FP32
+ * products with FP64 long sums.  BF16: BF16 storage, FP32 products, FP64 long
+ * sums.  The Cholesky factors, the iterates, the global step and the residuals
+ * are FP64 for every storage precision. */
+enum { BCA_F64 = 0, BCA_F32 = 1, BCA_BF16 = 2 };
+
+/* Where a buffer passed to the library lives. */
+enum { BCA_MEM_HOST = 0, BCA_MEM_DEVICE = 1 };
+
+/* Solver parameters.  The names follow the paper: gamma is the ridge weight of
+ * the SML problem (Sec. 2), rho_c the consensus penalty, rho_b the penalty of
+ * the bilinear constraint x^T s = t (Sec. 3), rho_l the penalty of the
+ * feature-split sub-solver (Sec. 3.1).  kappa bounds ||x||_0 (rows for softmax). */
+typedef struct {
+  int32_t loss;          /* BCA_LOSS_* */
+  int32_t n_features;    /* n >= 1 */
+  int32_t n_classes;     /* C: 1 unless softmax (2..64) */
+  int32_t n_partitions;  /* N >= 1 sample partitions */
+  int32_t n_blocks;      /* M >= 1 feature blocks per partition, M <= n */
+  int32_t kappa;         /* 1 <= kappa <= n */
+  const int64_t* rows;   /* host array of N entries: m_i >= 1; read by bca_create only */
+  double gamma, rho_c, rho_b, rho_l;   /* all > 0 */
+  int32_t inner_iters;   /* K_in >= 1 inner (Algorithm 2) iterations per outer iteration */
+  int32_t max_iters;     /* K >= 1: cap on outer iterations for bca_solve; size of the residual history */
+  double tol_p, tol_d, tol_b;          /* bca_solve stops when p_r <= tol_p, d_r <= tol_d, b_r <= tol_b */
+  int32_t a_dtype;       /* BCA_F64 / BCA_F32 / BCA_BF16 */
+  int32_t check_every;   /* bca_solve reads the residuals back every this many iterations (0 = 10) */
+  uint32_t flags;        /* reserved, must be 0 */
+} bca_params;
+
+/* Create a problem: validates the parameters and allocates device memory for
+ * the data and the ADMM state.  hip_stream is a hipStream_t (may be NULL).
+ * Errors: BCA_E_INVALID (parameter out of range), BCA_E_OOM, BCA_E_DEVICE. */
+int bca_create(const bca_params* params, void* hip_stream, bca_problem* out);
+
+/* Load partition `part` (0 <= part < N): A_i is m_i x n in the problem's a_dtype
+ * (row-major, row stride `ld` elements >= n; BF16 as uint16 bit patterns), b_i
+ * holds m_i doubles (squared: targets; logistic: labels -1/+1) or m_i int32
+ * class ids (softmax).  `mem` says whether A and b are host or device pointers;
+ * both are copied before the call returns (the copy is ordered on the problem's
+ * stream and the call synchronises it).  A partition may be loaded again until
+ * bca_finalize.
+ * Errors: BCA_E_INVALID (bad index, ld < n, label out of range),
+ * BCA_E_NONFINITE (NaN/Inf in A or b), BCA_E_STATE (after finalize). */
+int bca_set_data(bca_problem p, int32_t part, const void* A, int64_t ld, const void* b, int32_t mem);
+
+/* Setup of Sec. 3.1's x_ij-step, once per problem: for every partition i and
+ * block j the Gram matrix A_ij^T A_ij (MFMA), K_ij = rho_l A_ij^T A_ij +
+ * (1/(N gamma) + rho_c) I, its FP64 Cholesky factor L_ij and the inverse factor
+ * L_ij^-1 used by the triangular solves.  Resets the ADMM state to zero.
+ * Errors: BCA_E_STATE (a partition was never loaded), BCA_E_NONFINITE (K_ij not
+ * positive definite in FP64), BCA_E_DEVICE. */
+int bca_finalize(bca_problem p);
+
+/* Run `outer_iters` outer iterations of Algorithm 1: per partition K_in inner
+ * iterations of Algorithm 2 (x_ij ridge solves with the cached factors, block
+ * predictions averaged over the blocks, per-sample omega-bar prox, nu update),
+ * then the consensus average, the (z,t) step, the top-kappa s-step, the v- and
+ * u-updates and the residuals p_r, d_r, b_r (Sec. 3, Termination).  Enqueued
+ * asynchronously; *iters_done (may be NULL) gets the total outer iteration count.
+ * Errors: BCA_E_STATE (before finalize), BCA_E_INVALID. */
+int bca_step(bca_problem p, int32_t outer_iters, int32_t* iters_done);
+
+/* Iterate until p_r <= tol_p, d_r <= tol_d and b_r <= tol_b (tested every
+ * check_every iterations) or max_iters outer iterations in total.
+ * *converged = 1 if the tolerances were met.  Errors as bca_step, plus
+ * BCA_E_NONFINITE when an iterate became NaN/Inf. */
+int bca_solve(bca_problem p, int32_t* iters_done, int32_t* converged);
+
+/* The support T_kappa(z): the kappa largest |z_k| (row norms for softmax), ties
+ * to the lower index, ascending.  idx receives kappa int32 (host memory);
+ * *count = kappa. */
+int bca_get_support(bca_problem p, int32_t* idx, int32_t* count);
+
+/* The model x_hat = z restricted to T_kappa(z), zero elsewhere: n*C doubles
+ * (host memory, feature-major). */
+int bca_get_coef(bca_problem p, double* x);
+
+/* Residuals of the last outer iteration and its number (0 before any). */
+int bca_get_residuals(bca_problem p, double* pr, double* dr, double* br, int32_t* iter);
+
+/* Residual history: up to `cap` rows of (p_r, d_r, b_r), oldest first (host). */
+int bca_get_history(bca_problem p, double* hist, int32_t cap, int32_t* count);
+
+/* Objective of the SML problem (Sec. 2) at x_hat, in FP64. */
+int bca_get_objective(bca_problem p, double* f);
+
+/* Which state vector bca_get_vector / bca_set_vector address. */
+enum {
+  BCA_VEC_X = 0,      /* x_i, n*C, per partition */
+  BCA_VEC_U = 1,      /* u_i, n*C, per partition */
+  BCA_VEC_Z = 2,      /* z, n*C */
+  BCA_VEC_S = 3,      /* s, n (rows for softmax) */
+  BCA_VEC_OMEGA = 4,  /* omega-bar_i, m_i*C, per partition */
+  BCA_VEC_NU = 5,     /* nu_i, m_i*C, per partition */
+  BCA_VEC_TV = 6      /* the scalars (t, v): 2 doubles */
+};
+
+/* Copy one FP64 state vector to host memory (`part` ignored for global ones). */
+int bca_get_vector(bca_problem p, int32_t which, int32_t part, double* out);
+
+/* Overwrite one FP64 state vector from host memory.  After the last set, the
+ * next bca_step re-derives the cached block predictions from the new state. */
+int bca_set_vector(bca_problem p, int32_t which, int32_t part, const double* in);
+
+/* Checkpoint / resume of the whole ADMM state (x, u, z, s, t, v, omega-bar,
+ * nu, iteration count, residual history).  With buf == NULL, *bytes receives
+ * the size needed.  Resuming and continuing gives the same bits as an
+ * uninterrupted run. */
+int bca_get_state(bca_problem p, void* buf, size_t* bytes);
+int bca_set_state(bca_problem p, const void* buf, size_t bytes);
+
+/* The inverse Cholesky factor W_ij = L_ij^-1 of block (part, block), written
+ * dense row-major n_j x n_j (upper part zero) to host memory.  For tests of the
+ * setup: W^T W = K_ij^-1. */
+int bca_get_factor(bca_problem p, int32_t part, int32_t block, double* W);
+
+/* Kernel timing with HIP events on the problem's stream (off by default).
+ * Classes: 0 = A-streaming pass (block matvecs, prox, duals), 1 = block
+ * solves, 2 = global step, 3 = Gram, 4 = factorisation. */
+enum { BCA_KC_STREAM = 0, BCA_KC_SOLVE = 1, BCA_KC_GLOBAL = 2, BCA_KC_GRAM = 3, BCA_KC_FACTOR = 4 };
+int bca_set_timing(bca_problem p, int32_t on);
+int bca_get_timing(bca_problem p, int32_t kernel_class, int32_t* launches, double* total_ms);
+
+/* Release all device memory of the handle (NULL is accepted). */
+int bca_destroy(bca_problem p);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char* bca_last_error(void);
+
+/* The top-kappa projection of the s-step (Sec. 3), as a standalone device
+ * primitive: idx (device, kappa int32) receives the indices of the kappa
+ * largest |z_k| of the device vector z (n values, dtype BCA_F64 or BCA_F32),
+ * ties to the lower index, -0 equal to +0, ascending.  NaN inputs are not
+ * allowed.  Enqueued on hip_stream; synchronises it. */
+int bca_topk(const void* z, int32_t dtype, int64_t n, int32_t kappa, int32_t* idx, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BCA_H */

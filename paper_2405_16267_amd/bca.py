@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libbca.so (include/bca.h).
+
+Only argument marshalling happens here: every step of the solver runs in the
+library's HIP kernels.  Importing this module fails loudly when the library has
+not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbca.so")
+
+BCA_OK = 0
+ERRORS = {-1: "BCA_E_INVALID", -2: "BCA_E_OOM", -3: "BCA_E_STATE", -4: "BCA_E_NONFINITE",
+          -5: "BCA_E_DEVICE", -6: "BCA_E_BUDGET", -7: "BCA_E_NOTFOUND", -8: "BCA_E_CANCELLED"}
+LOSS = {"squared": 0, "logistic": 1, "softmax": 2}
+DTYPE = {"f64": 0, "f32": 1, "bf16": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+VEC_X, VEC_U, VEC_Z, VEC_S, VEC_OMEGA, VEC_NU, VEC_TV = range(7)
+KC_STREAM, KC_SOLVE, KC_GLOBAL, KC_GRAM, KC_FACTOR = range(5)
+
+EXPORTS = ["bca_create", "bca_set_data", "bca_finalize", "bca_step", "bca_solve",
+           "bca_get_support", "bca_get_coef", "bca_get_residuals", "bca_get_history",
+           "bca_get_objective", "bca_get_vector", "bca_set_vector", "bca_get_state",
+           "bca_set_state", "bca_get_factor", "bca_set_timing", "bca_get_timing", "bca_destroy",
+           "bca_last_error", "bca_topk"]
+
+
+class BcaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "BCA_E_?"), code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_int32), ("n_features", ctypes.c_int32),
+                ("n_classes", ctypes.c_int32), ("n_partitions", ctypes.c_int32),
+                ("n_blocks", ctypes.c_int32), ("kappa", ctypes.c_int32),
+                ("rows", ctypes.POINTER(ctypes.c_int64)),
+                ("gamma", ctypes.c_double), ("rho_c", ctypes.c_double),
+                ("rho_b", ctypes.c_double), ("rho_l", ctypes.c_double),
+                ("inner_iters", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("tol_p", ctypes.c_double), ("tol_d", ctypes.c_double), ("tol_b", ctypes.c_double),
+                ("a_dtype", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbca.so is not built (%s); run `python -m paper_2405_16267_amd.build`"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pi32, pdbl, psz = ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "bca_create": [ctypes.POINTER(Params), P, ctypes.POINTER(P)],
+        "bca_set_data": [P, i32, P, i64, P, i32],
+        "bca_finalize": [P],
+        "bca_step": [P, i32, pi32],
+        "bca_solve": [P, pi32, pi32],
+        "bca_get_support": [P, P, pi32],
+        "bca_get_coef": [P, P],
+        "bca_get_residuals": [P, pdbl, pdbl, pdbl, pi32],
+        "bca_get_history": [P, P, i32, pi32],
+        "bca_get_objective": [P, pdbl],
+        "bca_get_vector": [P, i32, i32, P],
+        "bca_set_vector": [P, i32, i32, P],
+        "bca_get_state": [P, P, psz],
+        "bca_set_state": [P, P, ctypes.c_size_t],
+        "bca_get_factor": [P, i32, i32, P],
+        "bca_set_timing": [P, i32],
+        "bca_get_timing": [P, i32, pi32, pdbl],
+        "bca_destroy": [P],
+        "bca_topk": [P, i32, i64, i32, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.bca_last_error.argtypes = []
+    lib.bca_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code: int):
+    if code != BCA_OK:
+        raise BcaError(code, _lib.bca_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return ctypes.c_void_p(None)
+
+
+_NP_DTYPE = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}
+
+
+class Problem:
+    """One Bi-cADMM problem: N sample partitions x M feature blocks on the GPU."""
+
+    def __init__(self, loss: str, n: int, rows: Sequence[int], n_blocks: int, kappa: int,
+                 gamma: float = 10.0, rho_c: float = 1.0, rho_b: float = 0.5,
+                 rho_l: float = 1.0, inner_iters: int = 5, max_iters: int = 100,
+                 dtype: str = "f32", n_classes: int = 1, tol=(1e-6, 1e-6, 1e-6),
+                 check_every: int = 10, stream=None):
+        self.loss, self.n, self.dtype = loss, n, dtype
+        self.rows = [int(r) for r in rows]
+        self.N, self.M, self.kappa, self.C = len(self.rows), n_blocks, kappa, n_classes
+        self.max_iters = max_iters
+        self._rows = (ctypes.c_int64 * self.N)(*self.rows)
+        p = Params(loss=LOSS[loss], n_features=n, n_classes=n_classes, n_partitions=self.N,
+                   n_blocks=n_blocks, kappa=kappa, rows=self._rows, gamma=gamma, rho_c=rho_c,
+                   rho_b=rho_b, rho_l=rho_l, inner_iters=inner_iters, max_iters=max_iters,
+                   tol_p=tol[0], tol_d=tol[1], tol_b=tol[2], a_dtype=DTYPE[dtype],
+                   check_every=check_every, flags=0)
+        self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(_lib.bca_create(ctypes.byref(p), self._stream, ctypes.byref(h)))
+        self._h = h
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.bca_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- data
+    def set_data(self, part: int, A, b):
+        """A: m_i x n (numpy in the storage dtype, or a contiguous torch CUDA tensor);
+        b: float64 targets/labels (int32 class ids for softmax), same placement."""
+        try:
+            import torch
+            is_t = isinstance(A, torch.Tensor)
+        except Exception:
+            is_t = False
+        if is_t:
+            assert A.is_cuda and b.is_cuda, "device tensors expected"
+            A = A.contiguous()
+            b = b.contiguous()
+            _check(_lib.bca_set_data(self._h, part, ctypes.c_void_p(A.data_ptr()), A.shape[1],
+                                     ctypes.c_void_p(b.data_ptr()), MEM_DEVICE))
+            return
+        A = np.ascontiguousarray(A, dtype=_NP_DTYPE[self.dtype])
+        b = np.ascontiguousarray(b, dtype=np.int32 if self.loss == "softmax" else np.float64)
+        if A.shape != (self.rows[part], self.n):
+            raise ValueError("partition %d: A has shape %s, expected %s"
+                             % (part, A.shape, (self.rows[part], self.n)))
+        _check(_lib.bca_set_data(self._h, part, _ptr(A), A.shape[1], _ptr(b), MEM_HOST))
+
+    def finalize(self):
+        _check(_lib.bca_finalize(self._h))
+
+    # -- iterations
+    def step(self, outer_iters: int = 1) -> int:
+        k = ctypes.c_int32()
+        _check(_lib.bca_step(self._h, outer_iters, ctypes.byref(k)))
+        return k.value
+
+    def solve(self):
+        k, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.bca_solve(self._h, ctypes.byref(k), ctypes.byref(c)))
+        return k.value, bool(c.value)
+
+    # -- queries
+    def support(self) -> np.ndarray:
+        idx = np.zeros(self.kappa, dtype=np.int32)
+        _check(_lib.bca_get_support(self._h, _ptr(idx), None))
+        return idx
+
+    def coef(self) -> np.ndarray:
+        x = np.zeros(self.n * self.C)
+        _check(_lib.bca_get_coef(self._h, _ptr(x)))
+        return x if self.C == 1 else x.reshape(self.n, self.C)
+
+    def residuals(self):
+        pr, dr, br, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(_lib.bca_get_residuals(self._h, ctypes.byref(pr), ctypes.byref(dr),
+                                      ctypes.byref(br), ctypes.byref(it)))
+        return pr.value, dr.value, br.value, it.value
+
+    def history(self) -> np.ndarray:
+        h = np.zeros((self.max_iters, 3))
+        k = ctypes.c_int32()
+        _check(_lib.bca_get_history(self._h, _ptr(h), self.max_iters, ctypes.byref(k)))
+        return h[:k.value]
+
+    def objective(self) -> float:
+        f = ctypes.c_double()
+        _check(_lib.bca_get_objective(self._h, ctypes.byref(f)))
+        return f.value
+
+    def _vlen(self, which, part):
+        if which in (VEC_X, VEC_U, VEC_Z):
+            return self.n * self.C
+        if which == VEC_S:
+            return self.n
+        if which in (VEC_OMEGA, VEC_NU):
+            return self.rows[part] * self.C
+        return 2
+
+    def get_vector(self, which: int, part: int = 0) -> np.ndarray:
+        out = np.zeros(self._vlen(which, part))
+        _check(_lib.bca_get_vector(self._h, which, part, _ptr(out)))
+        return out
+
+    def set_vector(self, which: int, part: int, values) -> None:
+        v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        if v.size != self._vlen(which, part):
+            raise ValueError("wrong length")
+        _check(_lib.bca_set_vector(self._h, which, part, _ptr(v)))
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(_lib.bca_get_state(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_lib.bca_get_state(self._h, buf, ctypes.byref(n)))
+        return buf.raw
+
+    def set_state(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(_lib.bca_set_state(self._h, buf, len(blob)))
+
+    def factor(self, part: int, block: int) -> np.ndarray:
+        q, r = divmod(self.n, self.M)
+        nj = q + (1 if block < r else 0)
+        W = np.zeros((nj, nj))
+        _check(_lib.bca_get_factor(self._h, part, block, _ptr(W)))
+        return W
+
+    def set_timing(self, on: bool = True):
+        _check(_lib.bca_set_timing(self._h, 1 if on else 0))
+
+    def timing(self, kernel_class: int):
+        n, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.bca_get_timing(self._h, kernel_class, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+
+def topk(z, kappa: int):
+    """Top-kappa indices (ascending) of |z| for a CUDA tensor z (float64/float32)."""
+    import torch
+    assert z.is_cuda and z.dim() == 1
+    z = z.contiguous()
+    dt = {torch.float64: 0, torch.float32: 1}[z.dtype]
+    idx = torch.empty(kappa, dtype=torch.int32, device=z.device)
+    _check(_lib.bca_topk(ctypes.c_void_p(z.data_ptr()), dt, z.numel(), kappa,
+                         ctypes.c_void_p(idx.data_ptr()), _current_stream()))
+    return idx

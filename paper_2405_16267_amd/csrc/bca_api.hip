@@ -1,0 +1,842 @@
+// Host runtime of the Bi-cADMM library: problem state, device memory plan,
+// the outer/inner iteration driver and the C ABI declared in include/bca.h.
+//
+// Device memory plan (all resident for the life of the handle):
+//   A        m_total x ld storage elements; partition i occupies rows
+//            [row_off[i], row_off[i+1]); block j is columns [col_off[j], col_off[j+1]);
+//            ld = n rounded up to 64 elements (columns >= n are zero and never read)
+//   b, omega-bar, nu          m_total doubles each
+//   x, u, rhs, tmp            N x n doubles;  xs: N x ld streaming copy of x
+//   z, s                      n doubles;  scal: t, v, p_r, d_r, b_r, iteration
+//   gpart                     N x Gp x ld doubles (per-workgroup partial A^T e)
+//   wr, wc                    packed W_ij = L_ij^-1 (rows, columns): sum_ij n_j (n_j + 1) / 2 each
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bca_internal.h"
+
+using namespace bca;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? BCA_E_OOM : BCA_E_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+size_t dtype_size(int d) { return d == BCA_F64 ? 8 : (d == BCA_F32 ? 4 : 2); }
+
+struct TimedPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct bca_problem_s {
+  bca_params p{};
+  hipStream_t stream = nullptr;
+  int n = 0, C = 1, N = 0, M = 0, kappa = 0, dtype = BCA_F32;
+  int64_t ld = 0, m_total = 0;
+  std::vector<int64_t> rows, row_off;
+  std::vector<int32_t> col_off;
+  std::vector<int64_t> fac_off, kmat_off;
+  int nj_max = 0, Gp = 1, nvec = 0;
+  int64_t fac_total = 0, kmat_total = 0;
+  double shift = 0.0;
+  // device buffers
+  void* A = nullptr;
+  double* b = nullptr;
+  int32_t* y = nullptr;
+  double *omega = nullptr, *nu = nullptr;
+  double *x = nullptr, *u = nullptr, *rhs = nullptr, *tmp = nullptr;
+  void* xs = nullptr;
+  void* xhat_s = nullptr;
+  double *z = nullptr, *s = nullptr, *scal = nullptr, *hist = nullptr, *work = nullptr;
+  int32_t* support = nullptr;
+  int* status = nullptr;
+  double* gpart = nullptr;
+  double *wr = nullptr, *wc = nullptr;
+  double* objpart = nullptr;
+  int64_t* d_row_off = nullptr;
+  int32_t* d_col_off = nullptr;
+  int64_t* d_fac_off = nullptr;
+  int64_t* d_kmat_off = nullptr;
+  // host state
+  std::vector<char> loaded;
+  bool finalized = false;
+  bool need_prime = false;
+  int iter = 0;
+  bool timing = false;
+  std::vector<TimedPair> pending[5];
+  int launches[5] = {0, 0, 0, 0, 0};
+  double total_ms[5] = {0, 0, 0, 0, 0};
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(bca_problem P, T** out, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) return fail(BCA_E_OOM, "hipMalloc(%zu bytes) failed: %s", count * sizeof(T), hipGetErrorString(e));
+  P->allocs.push_back(p);
+  *out = reinterpret_cast<T*>(p);
+  return BCA_OK;
+}
+
+void dfree(bca_problem P, void* p) {
+  if (!p) return;
+  (void)hipFree(p);
+  P->allocs.erase(std::remove(P->allocs.begin(), P->allocs.end(), p), P->allocs.end());
+}
+
+#define TRY(expr)          \
+  do {                     \
+    int rc_ = (expr);      \
+    if (rc_ != BCA_OK) return rc_; \
+  } while (0)
+
+int xs_is_f64(bca_problem P) { return P->dtype == BCA_F64 ? 1 : 0; }
+
+// Record a timing event pair around one launch when timing is on.
+struct Timer {
+  bca_problem P;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer(bca_problem P_, int cls_) : P(P_), cls(cls_) {
+    if (P->timing) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, P->stream);
+    }
+  }
+  ~Timer() {
+    if (P->timing) {
+      (void)hipEventRecord(b, P->stream);
+      P->pending[cls].push_back({a, b});
+      P->launches[cls] += 1;
+    }
+  }
+};
+
+void harvest_timing(bca_problem P) {
+  for (int c = 0; c < 5; ++c) {
+    for (auto& pr : P->pending[c]) {
+      (void)hipEventSynchronize(pr.b);
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess) P->total_ms[c] += ms;
+      (void)hipEventDestroy(pr.a);
+      (void)hipEventDestroy(pr.b);
+    }
+    P->pending[c].clear();
+  }
+}
+
+StreamArgs stream_args(bca_problem P, int mode) {
+  StreamArgs a{};
+  a.A = P->A;
+  a.ld = P->ld;
+  a.row_off = P->d_row_off;
+  a.b = P->b;
+  a.y = P->y;
+  a.omega = P->omega;
+  a.nu = P->nu;
+  a.xs = P->xs;
+  a.gpart = P->gpart;
+  a.N = P->N;
+  a.Gp = P->Gp;
+  a.nvec = P->nvec;
+  a.M = P->M;
+  a.C = P->C;
+  a.loss = P->p.loss;
+  a.inv_M = 1.0 / P->M;
+  a.rho_l = P->p.rho_l;
+  a.mode = mode;
+  return a;
+}
+
+SolveArgs solve_args(bca_problem P) {
+  SolveArgs a{};
+  a.gpart = P->gpart;
+  a.ld = P->ld;
+  a.Gp = P->Gp;
+  a.x = P->x;
+  a.xw = P->x;
+  a.xs = P->xs;
+  a.xs_f64 = xs_is_f64(P);
+  a.u = P->u;
+  a.z = P->z;
+  a.rhs = P->rhs;
+  a.tmp = P->tmp;
+  a.wr = P->wr;
+  a.wc = P->wc;
+  a.fac_off = P->d_fac_off;
+  a.col_off = P->d_col_off;
+  a.N = P->N;
+  a.M = P->M;
+  a.n = P->n;
+  a.C = P->C;
+  a.nj_max = P->nj_max;
+  a.rho_l = P->p.rho_l;
+  a.rho_c = P->p.rho_c;
+  a.shift = P->shift;
+  return a;
+}
+
+GlobalArgs global_args(bca_problem P) {
+  GlobalArgs g{};
+  g.x = P->x;
+  g.u = P->u;
+  g.z = P->z;
+  g.s = P->s;
+  g.scal = P->scal;
+  g.hist = P->hist;
+  g.support = P->support;
+  g.work = P->work;
+  g.status = P->status;
+  g.N = P->N;
+  g.n = P->n;
+  g.C = P->C;
+  g.kappa = P->kappa;
+  g.hist_cap = P->p.max_iters;
+  g.rho_c = P->p.rho_c;
+  g.rho_b = P->p.rho_b;
+  return g;
+}
+
+int launch_ok(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(BCA_E_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+  return BCA_OK;
+}
+
+int prime(bca_problem P) {
+  TRY(launch_ok(launch_make_xs(P->x, P->xs, xs_is_f64(P), P->N, P->n, P->C, P->ld, P->stream), "make_xs"));
+  Timer t(P, BCA_KC_STREAM);
+  TRY(launch_ok(launch_stream(stream_args(P, 1), P->dtype, P->stream), "stream(prime)"));
+  P->need_prime = false;
+  return BCA_OK;
+}
+
+int one_outer(bca_problem P) {
+  const SolveArgs sa = solve_args(P);
+  const StreamArgs st = stream_args(P, 0);
+  for (int k = 0; k < P->p.inner_iters; ++k) {
+    {
+      Timer t(P, BCA_KC_SOLVE);
+      TRY(launch_ok(launch_solve(sa, P->stream), "solve"));
+    }
+    {
+      Timer t(P, BCA_KC_STREAM);
+      TRY(launch_ok(launch_stream(st, P->dtype, P->stream), "stream"));
+    }
+  }
+  {
+    Timer t(P, BCA_KC_GLOBAL);
+    TRY(launch_ok(launch_global(global_args(P), P->stream), "global"));
+  }
+  P->iter += 1;
+  return BCA_OK;
+}
+
+int check_status(bca_problem P, const char* what) {
+  int st = 0;
+  HIP_TRY(hipMemcpyAsync(&st, P->status, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (st) return fail(BCA_E_NONFINITE, "%s: non-finite value encountered", what);
+  return BCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bca_last_error(void) { return g_err.c_str(); }
+
+int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
+  if (!prm || !out) return fail(BCA_E_INVALID, "null argument");
+  *out = nullptr;
+  const bca_params& p = *prm;
+  if (p.loss < 0 || p.loss > 2) return fail(BCA_E_INVALID, "unknown loss %d", p.loss);
+  if (p.loss == BCA_LOSS_SOFTMAX) return fail(BCA_E_INVALID, "softmax loss is not available in this build");
+  const int C = 1;
+  if (p.loss != BCA_LOSS_SOFTMAX && p.n_classes != 1 && p.n_classes != 0)
+    return fail(BCA_E_INVALID, "n_classes must be 1 for this loss");
+  if (p.n_features < 1) return fail(BCA_E_INVALID, "n_features must be >= 1");
+  if (p.n_partitions < 1) return fail(BCA_E_INVALID, "n_partitions must be >= 1");
+  if (p.n_blocks < 1 || p.n_blocks > p.n_features) return fail(BCA_E_INVALID, "need 1 <= n_blocks <= n_features");
+  if (p.kappa < 1 || p.kappa > p.n_features) return fail(BCA_E_INVALID, "need 1 <= kappa <= n_features");
+  if (!p.rows) return fail(BCA_E_INVALID, "rows is NULL");
+  if (!(p.gamma > 0) || !(p.rho_c > 0) || !(p.rho_b > 0) || !(p.rho_l > 0))
+    return fail(BCA_E_INVALID, "gamma, rho_c, rho_b, rho_l must be > 0");
+  if (p.inner_iters < 1 || p.max_iters < 1) return fail(BCA_E_INVALID, "inner_iters and max_iters must be >= 1");
+  if (p.a_dtype < 0 || p.a_dtype > 2) return fail(BCA_E_INVALID, "unknown a_dtype %d", p.a_dtype);
+  if (p.flags != 0) return fail(BCA_E_INVALID, "flags must be 0");
+  for (int i = 0; i < p.n_partitions; ++i)
+    if (p.rows[i] < 1) return fail(BCA_E_INVALID, "rows[%d] must be >= 1", i);
+
+  bca_problem P = new bca_problem_s();
+  P->p = p;
+  P->p.rows = nullptr;
+  P->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  P->n = p.n_features;
+  P->C = C;
+  P->N = p.n_partitions;
+  P->M = p.n_blocks;
+  P->kappa = p.kappa;
+  P->dtype = p.a_dtype;
+  P->ld = ((int64_t)P->n + 63) / 64 * 64;
+  P->rows.assign(p.rows, p.rows + P->N);
+  P->row_off.assign(P->N + 1, 0);
+  for (int i = 0; i < P->N; ++i) P->row_off[i + 1] = P->row_off[i] + P->rows[i];
+  P->m_total = P->row_off[P->N];
+  P->col_off.assign(P->M + 1, 0);
+  {
+    const int q = P->n / P->M, r = P->n % P->M;
+    for (int j = 0; j < P->M; ++j) P->col_off[j + 1] = P->col_off[j] + q + (j < r ? 1 : 0);
+  }
+  P->fac_off.resize((size_t)P->N * P->M);
+  P->kmat_off.resize((size_t)P->N * P->M);
+  int64_t fo = 0, ko = 0;
+  for (int i = 0; i < P->N; ++i)
+    for (int j = 0; j < P->M; ++j) {
+      const int64_t nj = P->col_off[j + 1] - P->col_off[j];
+      P->nj_max = std::max<int>(P->nj_max, (int)nj);
+      P->fac_off[(size_t)i * P->M + j] = fo;
+      P->kmat_off[(size_t)i * P->M + j] = ko;
+      fo += nj * (nj + 1) / 2;
+      ko += nj * nj;
+    }
+  P->fac_total = fo;
+  P->kmat_total = ko;
+  P->shift = 1.0 / (P->N * p.gamma) + p.rho_c;
+  const int VEC = (P->dtype == BCA_F64) ? 2 : (P->dtype == BCA_F32 ? 4 : 8);
+  P->nvec = (P->n + VEC - 1) / VEC;
+  {
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    const int occ = stream_occupancy_workgroups(P->dtype, P->nvec, C);
+    int64_t gp = (int64_t)occ * cus / P->N;
+    int64_t maxrows = 0;
+    for (auto r : P->rows) maxrows = std::max(maxrows, r);
+    gp = std::min<int64_t>(gp, (maxrows + 3) / 4);
+    P->Gp = (int)std::max<int64_t>(1, gp);
+  }
+  P->loaded.assign(P->N, 0);
+
+  const size_t es = dtype_size(P->dtype);
+  int rc = BCA_OK;
+  auto chk = [&](int r) {
+    if (rc == BCA_OK && r != BCA_OK) rc = r;
+  };
+  {
+    void* a = nullptr;
+    hipError_t e = hipMalloc(&a, (size_t)P->m_total * P->ld * es);
+    if (e != hipSuccess) chk(fail(BCA_E_OOM, "hipMalloc(A) failed: %s", hipGetErrorString(e)));
+    else {
+      P->allocs.push_back(a);
+      P->A = a;
+    }
+  }
+  if (rc == BCA_OK) chk(dalloc(P, &P->b, P->m_total));
+  if (rc == BCA_OK) chk(dalloc(P, &P->omega, (size_t)P->m_total * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->nu, (size_t)P->m_total * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->x, (size_t)P->N * P->n * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->u, (size_t)P->N * P->n * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->rhs, (size_t)P->N * P->n * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->tmp, (size_t)P->N * P->n * C));
+  if (rc == BCA_OK) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)P->N * P->ld * C * (xs_is_f64(P) ? 8 : 4));
+    if (e != hipSuccess) chk(fail(BCA_E_OOM, "hipMalloc(xs) failed"));
+    else { P->allocs.push_back(q); P->xs = q; }
+    e = hipMalloc(&q, (size_t)P->ld * C * (xs_is_f64(P) ? 8 : 4));
+    if (e != hipSuccess) chk(fail(BCA_E_OOM, "hipMalloc(xhat) failed"));
+    else { P->allocs.push_back(q); P->xhat_s = q; }
+  }
+  if (rc == BCA_OK) chk(dalloc(P, &P->z, (size_t)P->n * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->s, (size_t)P->n));
+  if (rc == BCA_OK) chk(dalloc(P, &P->scal, 8));
+  if (rc == BCA_OK) chk(dalloc(P, &P->hist, (size_t)p.max_iters * 3));
+  if (rc == BCA_OK) chk(dalloc(P, &P->work, (size_t)P->n * 6));
+  if (rc == BCA_OK) chk(dalloc(P, &P->support, (size_t)P->kappa));
+  if (rc == BCA_OK) chk(dalloc(P, &P->status, 4));
+  if (rc == BCA_OK) chk(dalloc(P, &P->gpart, (size_t)P->N * P->Gp * P->ld * C));
+  if (rc == BCA_OK) chk(dalloc(P, &P->wr, (size_t)P->fac_total));
+  if (rc == BCA_OK) chk(dalloc(P, &P->wc, (size_t)P->fac_total));
+  if (rc == BCA_OK) chk(dalloc(P, &P->objpart, (size_t)P->N * P->Gp));
+  if (rc == BCA_OK) chk(dalloc(P, &P->d_row_off, P->N + 1));
+  if (rc == BCA_OK) chk(dalloc(P, &P->d_col_off, P->M + 1));
+  if (rc == BCA_OK) chk(dalloc(P, &P->d_fac_off, (size_t)P->N * P->M));
+  if (rc == BCA_OK) chk(dalloc(P, &P->d_kmat_off, (size_t)P->N * P->M));
+  if (rc != BCA_OK) {
+    std::string msg = g_err;
+    bca_destroy(P);
+    g_err = msg;
+    return rc;
+  }
+  hipStream_t s = P->stream;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = cp(P->d_row_off, P->row_off.data(), (P->N + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = cp(P->d_col_off, P->col_off.data(), (P->M + 1) * sizeof(int32_t));
+  if (e == hipSuccess) e = cp(P->d_fac_off, P->fac_off.data(), P->fac_off.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = cp(P->d_kmat_off, P->kmat_off.data(), P->kmat_off.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemsetAsync(P->A, 0, (size_t)P->m_total * P->ld * es, s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->status, 0, 4 * sizeof(int), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    bca_destroy(P);
+    return fail(BCA_E_DEVICE, "create: %s", hipGetErrorString(e));
+  }
+  *out = P;
+  return BCA_OK;
+}
+
+int bca_set_data(bca_problem P, int32_t part, const void* A, int64_t ld, const void* b, int32_t mem) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (P->finalized) return fail(BCA_E_STATE, "set_data after finalize");
+  if (part < 0 || part >= P->N) return fail(BCA_E_INVALID, "partition %d out of range", part);
+  if (!A || !b) return fail(BCA_E_INVALID, "null data pointer");
+  if (ld < P->n) return fail(BCA_E_INVALID, "ld %lld < n %d", (long long)ld, P->n);
+  if (mem != BCA_MEM_HOST && mem != BCA_MEM_DEVICE) return fail(BCA_E_INVALID, "bad mem kind");
+  const size_t es = dtype_size(P->dtype);
+  const int64_t m = P->rows[part];
+  const hipMemcpyKind kind = mem == BCA_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  char* dstA = reinterpret_cast<char*>(P->A) + (size_t)P->row_off[part] * P->ld * es;
+  HIP_TRY(hipMemcpy2DAsync(dstA, P->ld * es, A, ld * es, P->n * es, m, kind, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->b + P->row_off[part], b, m * sizeof(double), kind, P->stream));
+  HIP_TRY(hipMemsetAsync(P->status + 1, 0, sizeof(int), P->stream));
+  TRY(launch_ok(launch_check(dstA, P->dtype, m * P->ld, P->status + 1, P->stream), "check"));
+  TRY(launch_ok(launch_check(P->b + P->row_off[part], BCA_F64, m, P->status + 1, P->stream), "check"));
+  if (P->p.loss == BCA_LOSS_LOGISTIC) {
+    HIP_TRY(hipMemsetAsync(P->status + 2, 0, sizeof(int), P->stream));
+    TRY(launch_ok(launch_check_signs(P->b + P->row_off[part], m, P->status + 2, P->stream), "check"));
+  }
+  int flags[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(flags, P->status + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  if (flags[0]) {
+    P->loaded[part] = 0;
+    return fail(BCA_E_NONFINITE, "partition %d: NaN/Inf in A or b", part);
+  }
+  if (P->p.loss == BCA_LOSS_LOGISTIC && flags[1]) {
+    P->loaded[part] = 0;
+    return fail(BCA_E_INVALID, "partition %d: logistic labels must be -1 or +1", part);
+  }
+  P->loaded[part] = 1;
+  return BCA_OK;
+}
+
+int bca_finalize(bca_problem P) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (P->finalized) return fail(BCA_E_STATE, "already finalized");
+  for (int i = 0; i < P->N; ++i)
+    if (!P->loaded[i]) return fail(BCA_E_STATE, "partition %d has no data", i);
+  double *kbuf = nullptr, *wbuf = nullptr;
+  TRY(dalloc(P, &kbuf, (size_t)P->kmat_total));
+  int rc = dalloc(P, &wbuf, (size_t)P->kmat_total);
+  if (rc != BCA_OK) {
+    dfree(P, kbuf);
+    return rc;
+  }
+  hipStream_t s = P->stream;
+  hipError_t e = hipMemsetAsync(wbuf, 0, (size_t)P->kmat_total * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->status, 0, sizeof(int), s);
+  GramArgs g{};
+  g.A = P->A;
+  g.ld = P->ld;
+  g.row_off = P->d_row_off;
+  g.col_off = P->d_col_off;
+  g.kmat_off = P->d_kmat_off;
+  g.kbuf = kbuf;
+  g.N = P->N;
+  g.M = P->M;
+  g.tiles_max = (P->nj_max + 63) / 64;
+  g.rho_l = P->p.rho_l;
+  g.shift = P->shift;
+  FactorArgs f{};
+  f.kbuf = kbuf;
+  f.wbuf = wbuf;
+  f.kmat_off = P->d_kmat_off;
+  f.col_off = P->d_col_off;
+  f.wr = P->wr;
+  f.wc = P->wc;
+  f.fac_off = P->d_fac_off;
+  f.status = P->status;
+  f.N = P->N;
+  f.M = P->M;
+  f.nj_max = P->nj_max;
+  if (e == hipSuccess) {
+    Timer t(P, BCA_KC_GRAM);
+    e = launch_gram(g, P->dtype, s);
+  }
+  if (e == hipSuccess) {
+    Timer t(P, BCA_KC_FACTOR);
+    e = launch_cholesky(f, s);
+    if (e == hipSuccess) e = launch_inverse(f, s);
+    if (e == hipSuccess) e = launch_pack(f, s);
+  }
+  // zero ADMM state (all-zero start); A^T e = 0 for it
+  const size_t nx = (size_t)P->N * P->n * P->C;
+  if (e == hipSuccess) e = hipMemsetAsync(P->x, 0, nx * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->u, 0, nx * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->z, 0, (size_t)P->n * P->C * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->s, 0, (size_t)P->n * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->scal, 0, 8 * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->hist, 0, (size_t)P->p.max_iters * 3 * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->omega, 0, (size_t)P->m_total * P->C * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->nu, 0, (size_t)P->m_total * P->C * sizeof(double), s);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(P->xs, 0, (size_t)P->N * P->ld * P->C * (xs_is_f64(P) ? 8 : 4), s);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(P->gpart, 0, (size_t)P->N * P->Gp * P->ld * P->C * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->support, 0, (size_t)P->kappa * sizeof(int32_t), s);
+  int st = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&st, P->status, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(P, kbuf);
+  dfree(P, wbuf);
+  if (e != hipSuccess) return fail(BCA_E_DEVICE, "finalize: %s", hipGetErrorString(e));
+  if (st) return fail(BCA_E_NONFINITE, "finalize: a block matrix K_ij is not positive definite");
+  P->finalized = true;
+  P->need_prime = false;
+  P->iter = 0;
+  return BCA_OK;
+}
+
+int bca_step(bca_problem P, int32_t outer_iters, int32_t* iters_done) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (!P->finalized) return fail(BCA_E_STATE, "step before finalize");
+  if (outer_iters < 0) return fail(BCA_E_INVALID, "negative iteration count");
+  if (P->need_prime) TRY(prime(P));
+  for (int k = 0; k < outer_iters; ++k) TRY(one_outer(P));
+  if (iters_done) *iters_done = P->iter;
+  return BCA_OK;
+}
+
+int bca_solve(bca_problem P, int32_t* iters_done, int32_t* converged) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (!P->finalized) return fail(BCA_E_STATE, "solve before finalize");
+  const int every = P->p.check_every > 0 ? P->p.check_every : 10;
+  int conv = 0;
+  if (P->need_prime) TRY(prime(P));
+  while (P->iter < P->p.max_iters) {
+    const int k = std::min(every, P->p.max_iters - P->iter);
+    for (int q = 0; q < k; ++q) TRY(one_outer(P));
+    double sc[6];
+    HIP_TRY(hipMemcpyAsync(sc, P->scal, sizeof(sc), hipMemcpyDeviceToHost, P->stream));
+    TRY(check_status(P, "solve"));
+    if (sc[2] <= P->p.tol_p && sc[3] <= P->p.tol_d && sc[4] <= P->p.tol_b) {
+      conv = 1;
+      break;
+    }
+  }
+  if (iters_done) *iters_done = P->iter;
+  if (converged) *converged = conv;
+  return BCA_OK;
+}
+
+int bca_get_support(bca_problem P, int32_t* idx, int32_t* count) {
+  if (!P || !idx) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "no solution before finalize");
+  if (P->iter == 0) {
+    // T_kappa of the zero vector: the first kappa indices
+    for (int k = 0; k < P->kappa; ++k) idx[k] = k;
+  } else {
+    HIP_TRY(hipMemcpyAsync(idx, P->support, P->kappa * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  if (count) *count = P->kappa;
+  return BCA_OK;
+}
+
+int bca_get_coef(bca_problem P, double* x) {
+  if (!P || !x) return fail(BCA_E_INVALID, "null argument");
+  std::vector<int32_t> idx(P->kappa);
+  TRY(bca_get_support(P, idx.data(), nullptr));
+  std::vector<double> z((size_t)P->n * P->C);
+  HIP_TRY(hipMemcpyAsync(z.data(), P->z, z.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  std::fill(x, x + (size_t)P->n * P->C, 0.0);
+  for (int k = 0; k < P->kappa; ++k)
+    for (int c = 0; c < P->C; ++c) x[(size_t)idx[k] * P->C + c] = z[(size_t)idx[k] * P->C + c];
+  return BCA_OK;
+}
+
+int bca_get_residuals(bca_problem P, double* pr, double* dr, double* br, int32_t* iter) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  double sc[6] = {0, 0, 0, 0, 0, 0};
+  if (P->finalized) {
+    HIP_TRY(hipMemcpyAsync(sc, P->scal, sizeof(sc), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  if (pr) *pr = sc[2];
+  if (dr) *dr = sc[3];
+  if (br) *br = sc[4];
+  if (iter) *iter = (int32_t)sc[5];
+  return BCA_OK;
+}
+
+int bca_get_history(bca_problem P, double* hist, int32_t cap, int32_t* count) {
+  if (!P || !hist) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) {
+    if (count) *count = 0;
+    return BCA_OK;
+  }
+  const int k = std::min<int>(std::min(P->iter, P->p.max_iters), cap);
+  if (k > 0) {
+    HIP_TRY(hipMemcpyAsync(hist, P->hist, (size_t)k * 3 * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  if (count) *count = k;
+  return BCA_OK;
+}
+
+int bca_get_objective(bca_problem P, double* f) {
+  if (!P || !f) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "objective before finalize");
+  std::vector<double> xh((size_t)P->n * P->C);
+  TRY(bca_get_coef(P, xh.data()));
+  // streaming copy of x_hat in the arithmetic type of the A stream
+  const size_t cnt = (size_t)P->ld * P->C;
+  if (xs_is_f64(P)) {
+    std::vector<double> h(cnt, 0.0);
+    std::copy(xh.begin(), xh.end(), h.begin());
+    HIP_TRY(hipMemcpyAsync(P->xhat_s, h.data(), cnt * 8, hipMemcpyHostToDevice, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  } else {
+    std::vector<float> h(cnt, 0.f);
+    for (size_t k = 0; k < xh.size(); ++k) h[k] = (float)xh[k];
+    HIP_TRY(hipMemcpyAsync(P->xhat_s, h.data(), cnt * 4, hipMemcpyHostToDevice, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+  }
+  ObjArgs o{};
+  o.A = P->A;
+  o.ld = P->ld;
+  o.row_off = P->d_row_off;
+  o.b = P->b;
+  o.y = P->y;
+  o.xs = P->xhat_s;
+  o.partial = P->objpart;
+  o.N = P->N;
+  o.Gp = P->Gp;
+  o.nvec = P->nvec;
+  o.C = P->C;
+  o.loss = P->p.loss;
+  TRY(launch_ok(launch_objective(o, P->dtype, P->stream), "objective"));
+  std::vector<double> part((size_t)P->N * P->Gp);
+  HIP_TRY(hipMemcpyAsync(part.data(), P->objpart, part.size() * 8, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  double acc = 0.0;
+  for (double v : part) acc += v;
+  double nn = 0.0;
+  for (double v : xh) nn += v * v;
+  *f = acc + nn / (2.0 * P->p.gamma);
+  return BCA_OK;
+}
+
+static int vec_target(bca_problem P, int32_t which, int32_t part, double** ptr, size_t* count) {
+  const size_t nx = (size_t)P->n * P->C;
+  switch (which) {
+    case BCA_VEC_X:
+    case BCA_VEC_U:
+      if (part < 0 || part >= P->N) return fail(BCA_E_INVALID, "partition out of range");
+      *ptr = (which == BCA_VEC_X ? P->x : P->u) + (size_t)part * nx;
+      *count = nx;
+      return BCA_OK;
+    case BCA_VEC_Z: *ptr = P->z; *count = nx; return BCA_OK;
+    case BCA_VEC_S: *ptr = P->s; *count = P->n; return BCA_OK;
+    case BCA_VEC_OMEGA:
+    case BCA_VEC_NU:
+      if (part < 0 || part >= P->N) return fail(BCA_E_INVALID, "partition out of range");
+      *ptr = (which == BCA_VEC_OMEGA ? P->omega : P->nu) + (size_t)P->row_off[part] * P->C;
+      *count = (size_t)P->rows[part] * P->C;
+      return BCA_OK;
+    case BCA_VEC_TV: *ptr = P->scal; *count = 2; return BCA_OK;
+    default: return fail(BCA_E_INVALID, "unknown vector id %d", which);
+  }
+}
+
+int bca_get_vector(bca_problem P, int32_t which, int32_t part, double* out) {
+  if (!P || !out) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "no state before finalize");
+  double* src;
+  size_t cnt;
+  TRY(vec_target(P, which, part, &src, &cnt));
+  HIP_TRY(hipMemcpyAsync(out, src, cnt * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return BCA_OK;
+}
+
+int bca_set_vector(bca_problem P, int32_t which, int32_t part, const double* in) {
+  if (!P || !in) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "no state before finalize");
+  double* dst;
+  size_t cnt;
+  TRY(vec_target(P, which, part, &dst, &cnt));
+  for (size_t k = 0; k < cnt; ++k)
+    if (!std::isfinite(in[k])) return fail(BCA_E_NONFINITE, "non-finite state value");
+  HIP_TRY(hipMemcpyAsync(dst, in, cnt * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  P->need_prime = true;
+  return BCA_OK;
+}
+
+// State blob: header, then x, u, z, s, (t, v), omega, nu, residual history.
+struct StateHeader {
+  uint64_t magic;
+  int32_t n, C, N, kappa;
+  int64_t m_total;
+  int32_t iter, hist_cap;
+  double scal[6];
+};
+static const uint64_t kStateMagic = 0x4243414453544131ull;  // "BCADSTA1"
+
+int bca_get_state(bca_problem P, void* buf, size_t* bytes) {
+  if (!P || !bytes) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "no state before finalize");
+  const size_t nx = (size_t)P->n * P->C, nm = (size_t)P->m_total * P->C;
+  const size_t need = sizeof(StateHeader) + 8 * (2 * P->N * nx + nx + P->n + 2 * nm + 3 * (size_t)P->p.max_iters);
+  if (!buf) {
+    *bytes = need;
+    return BCA_OK;
+  }
+  if (*bytes < need) return fail(BCA_E_INVALID, "state buffer too small (%zu < %zu)", *bytes, need);
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.n = P->n;
+  h.C = P->C;
+  h.N = P->N;
+  h.kappa = P->kappa;
+  h.m_total = P->m_total;
+  h.iter = P->iter;
+  h.hist_cap = P->p.max_iters;
+  char* o = reinterpret_cast<char*>(buf);
+  HIP_TRY(hipMemcpyAsync(h.scal, P->scal, sizeof(h.scal), hipMemcpyDeviceToHost, P->stream));
+  double* d = reinterpret_cast<double*>(o + sizeof(StateHeader));
+  HIP_TRY(hipMemcpyAsync(d, P->x, P->N * nx * 8, hipMemcpyDeviceToHost, P->stream)); d += P->N * nx;
+  HIP_TRY(hipMemcpyAsync(d, P->u, P->N * nx * 8, hipMemcpyDeviceToHost, P->stream)); d += P->N * nx;
+  HIP_TRY(hipMemcpyAsync(d, P->z, nx * 8, hipMemcpyDeviceToHost, P->stream)); d += nx;
+  HIP_TRY(hipMemcpyAsync(d, P->s, P->n * 8, hipMemcpyDeviceToHost, P->stream)); d += P->n;
+  HIP_TRY(hipMemcpyAsync(d, P->omega, nm * 8, hipMemcpyDeviceToHost, P->stream)); d += nm;
+  HIP_TRY(hipMemcpyAsync(d, P->nu, nm * 8, hipMemcpyDeviceToHost, P->stream)); d += nm;
+  HIP_TRY(hipMemcpyAsync(d, P->hist, (size_t)P->p.max_iters * 3 * 8, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  std::memcpy(o, &h, sizeof(h));
+  *bytes = need;
+  return BCA_OK;
+}
+
+int bca_set_state(bca_problem P, const void* buf, size_t bytes) {
+  if (!P || !buf) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "set_state before finalize");
+  StateHeader h;
+  if (bytes < sizeof(h)) return fail(BCA_E_INVALID, "state blob too small");
+  std::memcpy(&h, buf, sizeof(h));
+  const size_t nx = (size_t)P->n * P->C, nm = (size_t)P->m_total * P->C;
+  const size_t need = sizeof(StateHeader) + 8 * (2 * P->N * nx + nx + P->n + 2 * nm + 3 * (size_t)P->p.max_iters);
+  if (h.magic != kStateMagic || h.n != P->n || h.C != P->C || h.N != P->N || h.kappa != P->kappa ||
+      h.m_total != P->m_total || h.hist_cap != P->p.max_iters || bytes < need)
+    return fail(BCA_E_INVALID, "state blob does not match this problem");
+  const double* d = reinterpret_cast<const double*>(reinterpret_cast<const char*>(buf) + sizeof(StateHeader));
+  HIP_TRY(hipMemcpyAsync(P->scal, h.scal, sizeof(h.scal), hipMemcpyHostToDevice, P->stream));
+  HIP_TRY(hipMemcpyAsync(P->x, d, P->N * nx * 8, hipMemcpyHostToDevice, P->stream)); d += P->N * nx;
+  HIP_TRY(hipMemcpyAsync(P->u, d, P->N * nx * 8, hipMemcpyHostToDevice, P->stream)); d += P->N * nx;
+  HIP_TRY(hipMemcpyAsync(P->z, d, nx * 8, hipMemcpyHostToDevice, P->stream)); d += nx;
+  HIP_TRY(hipMemcpyAsync(P->s, d, P->n * 8, hipMemcpyHostToDevice, P->stream)); d += P->n;
+  HIP_TRY(hipMemcpyAsync(P->omega, d, nm * 8, hipMemcpyHostToDevice, P->stream)); d += nm;
+  HIP_TRY(hipMemcpyAsync(P->nu, d, nm * 8, hipMemcpyHostToDevice, P->stream)); d += nm;
+  HIP_TRY(hipMemcpyAsync(P->hist, d, (size_t)P->p.max_iters * 3 * 8, hipMemcpyHostToDevice, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  P->iter = h.iter;
+  // support of the restored z
+  if (P->iter > 0) {
+    TRY(launch_ok(launch_topk(P->z, 1, P->n, P->kappa, P->support, P->work, P->stream), "topk"));
+  }
+  P->need_prime = true;
+  return BCA_OK;
+}
+
+int bca_get_factor(bca_problem P, int32_t part, int32_t block, double* W) {
+  if (!P || !W) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "no factor before finalize");
+  if (part < 0 || part >= P->N || block < 0 || block >= P->M) return fail(BCA_E_INVALID, "index out of range");
+  const int64_t nj = P->col_off[block + 1] - P->col_off[block];
+  std::vector<double> pk((size_t)(nj * (nj + 1) / 2));
+  HIP_TRY(hipMemcpyAsync(pk.data(), P->wr + P->fac_off[(size_t)part * P->M + block], pk.size() * 8,
+                         hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  for (int64_t r = 0; r < nj; ++r)
+    for (int64_t c = 0; c < nj; ++c) W[r * nj + c] = c <= r ? pk[(size_t)(r * (r + 1) / 2 + c)] : 0.0;
+  return BCA_OK;
+}
+
+int bca_set_timing(bca_problem P, int32_t on) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  harvest_timing(P);
+  P->timing = on != 0;
+  for (int c = 0; c < 5; ++c) {
+    P->launches[c] = 0;
+    P->total_ms[c] = 0.0;
+  }
+  return BCA_OK;
+}
+
+int bca_get_timing(bca_problem P, int32_t kernel_class, int32_t* launches, double* total_ms) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (kernel_class < 0 || kernel_class >= 5) return fail(BCA_E_INVALID, "bad kernel class");
+  harvest_timing(P);
+  if (launches) *launches = P->launches[kernel_class];
+  if (total_ms) *total_ms = P->total_ms[kernel_class];
+  return BCA_OK;
+}
+
+int bca_destroy(bca_problem P) {
+  if (!P) return BCA_OK;
+  if (P->stream || true) (void)hipStreamSynchronize(P->stream);
+  harvest_timing(P);
+  for (void* p : P->allocs) (void)hipFree(p);
+  P->allocs.clear();
+  delete P;
+  return BCA_OK;
+}
+
+int bca_topk(const void* z, int32_t dtype, int64_t n, int32_t kappa, int32_t* idx, void* hip_stream) {
+  if (!z || !idx) return fail(BCA_E_INVALID, "null argument");
+  if (dtype != BCA_F64 && dtype != BCA_F32) return fail(BCA_E_INVALID, "dtype must be F64 or F32");
+  if (n < 1 || kappa < 1 || kappa > n) return fail(BCA_E_INVALID, "need 1 <= kappa <= n");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  TRY(launch_ok(launch_topk(z, dtype == BCA_F64, n, kappa, idx, nullptr, s), "topk"));
+  HIP_TRY(hipStreamSynchronize(s));
+  return BCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+// Internal declarations of the Bi-cADMM HIP library: storage traits, kernel
+// argument blocks and the host-side launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bca.h"
+
+namespace bca {
+
+// BF16 storage tag: the upper 16 bits of an IEEE binary32.
+struct bf16_t {
+  uint16_t bits;
+};
+
+// Per storage type: 16-byte vector used to stream A, elements per vector,
+// arithmetic type of the products (and of the streaming copy of x).
+template <typename T>
+struct Traits;
+template <>
+struct Traits<double> {
+  using vec_t = double2;
+  using acc_t = double;
+  static constexpr int VEC = 2;
+};
+template <>
+struct Traits<float> {
+  using vec_t = float4;
+  using acc_t = float;
+  static constexpr int VEC = 4;
+};
+template <>
+struct Traits<bf16_t> {
+  using vec_t = uint4;
+  using acc_t = float;
+  static constexpr int VEC = 8;
+};
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// Element e of a 16-byte vector, as the arithmetic type.
+__device__ __forceinline__ double vget(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+__device__ __forceinline__ float vget(const float4& v, int e) {
+  return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ float vget(const uint4& v, int e) {
+  uint32_t w = (e >> 1) == 0 ? v.x : ((e >> 1) == 1 ? v.y : ((e >> 1) == 2 ? v.z : v.w));
+  return (e & 1) ? bf16_hi(w) : bf16_lo(w);
+}
+
+template <typename V>
+__device__ __forceinline__ V vzero();
+template <>
+__device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+template <>
+__device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <>
+__device__ __forceinline__ uint4 vzero<uint4>() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// Sum over the 64 lanes of a wavefront (every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ kernels
+// One pass over A per inner iteration (Algorithm 2): block predictions,
+// sample-space average, omega-bar prox, nu update, e = omega - a - nu, and the
+// per-workgroup partial sums of A^T e for the next x_ij-step.
+struct StreamArgs {
+  const void* A;           // all partitions, row-major, m_total x ld
+  int64_t ld;              // row stride (elements)
+  const int64_t* row_off;  // N + 1 row offsets (device)
+  const double* b;         // m_total targets / labels
+  const int32_t* y;        // m_total class ids (softmax)
+  double* omega;           // m_total x C
+  double* nu;              // m_total x C
+  const void* xs;          // N x ld x C streaming copy of x (FP64 or FP32)
+  double* gpart;           // N x Gp x ld x C partial sums of A^T e
+  int N, Gp, nvec, M, C, loss;
+  double inv_M, rho_l;
+  int mode;                // 0: inner iteration; 1: prime (e from stored state, no prox)
+};
+
+// Objective: per-workgroup partial loss sums of l(A_i xhat; b_i).
+struct ObjArgs {
+  const void* A;
+  int64_t ld;
+  const int64_t* row_off;
+  const double* b;
+  const int32_t* y;
+  const void* xs;          // x_hat streaming copy, ld x C (shared by all partitions)
+  double* partial;         // N x Gp
+  int N, Gp, nvec, C, loss;
+};
+
+struct Problem;  // host-side problem (bca_api.hip)
+
+// Launchers (host side).  Each returns hipSuccess or the launch error.
+hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s);
+hipError_t launch_objective(const ObjArgs& a, int dtype, hipStream_t s);
+int stream_occupancy_workgroups(int dtype, int nvec, int C);   // resident workgroups per CU
+
+struct GramArgs {
+  const void* A;
+  int64_t ld;
+  const int64_t* row_off;  // N + 1
+  const int32_t* col_off;  // M + 1
+  const int64_t* kmat_off; // N*M offsets (doubles) of each K_ij in kbuf
+  double* kbuf;            // K_ij dense n_j x n_j row-major (lower part written)
+  int N, M, tiles_max;     // tiles_max = ceil(max n_j / 64)
+  double rho_l, shift;     // K = rho_l G + shift I
+};
+hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s);
+
+struct FactorArgs {
+  double* kbuf;            // in: K_ij (lower); out: L_ij (lower)
+  double* wbuf;            // out: W_ij = L_ij^-1 dense (lower)
+  const int64_t* kmat_off; // N*M
+  const int32_t* col_off;  // M + 1
+  double* wr;              // packed lower rows of W_ij
+  double* wc;              // packed lower columns of W_ij (rows of W_ij^T)
+  const int64_t* fac_off;  // N*M offsets (doubles) into wr / wc
+  int* status;             // set nonzero if a pivot is not positive
+  int N, M, nj_max;
+};
+hipError_t launch_cholesky(const FactorArgs& a, hipStream_t s);
+hipError_t launch_inverse(const FactorArgs& a, hipStream_t s);
+hipError_t launch_pack(const FactorArgs& a, hipStream_t s);
+
+struct SolveArgs {
+  const double* gpart;     // N x Gp x ld x C
+  int64_t ld;
+  int Gp;
+  const double* x;         // N x n x C
+  double* xw;              // x updated in place (same as x)
+  void* xs;                // streaming copy N x ld x C (FP32 or FP64)
+  int xs_f64;
+  const double* u;         // N x n x C
+  const double* z;         // n x C
+  double* rhs;             // N x n x C
+  double* tmp;             // N x n x C
+  const double* wr;
+  const double* wc;
+  const int64_t* fac_off;  // N*M
+  const int32_t* col_off;  // M + 1
+  int N, M, n, C, nj_max;
+  double rho_l, rho_c, shift;
+};
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+
+struct GlobalArgs {
+  double* x;               // N x n x C
+  double* u;               // N x n x C
+  double* z;               // n x C
+  double* s;               // n
+  double* scal;            // [0] t, [1] v, [2] pr, [3] dr, [4] br, [5] iter (as double)
+  double* hist;            // hist_cap x 3
+  int32_t* support;        // kappa
+  double* work;            // scratch: 6 n doubles
+  int* status;             // nonzero on NaN/Inf
+  int N, n, C, kappa, hist_cap;
+  double rho_c, rho_b;
+};
+hipError_t launch_global(const GlobalArgs& a, hipStream_t s);
+
+hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* idx, double* work,
+                       hipStream_t s);
+
+// Non-finite scan of a device buffer of `count` elements (dtype BCA_*), plus an
+// optional label range check; sets *flag nonzero if anything is off.
+hipError_t launch_check(const void* p, int dtype, int64_t count, int* flag, hipStream_t s);
+hipError_t launch_check_labels(const int32_t* y, int64_t count, int C, int* flag, hipStream_t s);
+hipError_t launch_check_signs(const double* b, int64_t count, int* flag, hipStream_t s);
+
+// Streaming copy of x: xs[i][k*C + c] = x[i][k*C + c] for k < n, in FP64 or FP32.
+hipError_t launch_make_xs(const double* x, void* xs, int xs_f64, int N, int n, int C, int64_t ld,
+                          hipStream_t s);
+
+}  // namespace bca

@@ -1,0 +1,421 @@
+// Global level of Algorithm 1 plus the node-level u-update, fused into one
+// workgroup of 1024 threads (the work is O(N n) and latency-bound):
+//   wbar = (1/N) sum_i (x_i + u_i)                         consensus average
+//   (z, t) = argmin_{||z||_1 <= t} (a/2)||z - wbar||^2 + (rho_b/2)(s^T z - t + v)^2
+//   s = clip((t - v)/M_kappa, -1, 1) sign(z) on T_kappa(z)  (s-step, Sec. 3)
+//   v += z^T s - t;  u_i += x_i - z;  p_r, d_r, b_r          (Termination, Sec. 3)
+// with a = N rho_c.  The (z, t) problem is strictly convex; from its KKT
+// conditions z(theta) = S_{theta/a}(wbar + theta s / a) and theta >= 0 is the
+// root of the increasing piecewise-linear
+//   psi(theta) = v + theta / rho_b + sum_{k: theta_k > theta} (theta d_k^2 / a - d_k |wbar_k|),
+//   d_k = 1 - sign(wbar_k) s_k,  theta_k = a |wbar_k| / d_k (breakpoints).
+// The root is bracketed by multisection until no breakpoint lies inside the
+// bracket, then read off exactly from the linear piece.
+// T_kappa is a radix select on the bit patterns of |z_k| (FP64 bits with the
+// sign cleared, so -0 == +0), ties resolved toward the lower index.
+#include "bca_internal.h"
+
+namespace bca {
+
+constexpr int GT = 1024;
+constexpr int GW = GT / 64;
+constexpr int PSECT = 15;  // interior points per multisection round
+
+// Sum of one value per thread; every thread receives the same total (fixed order).
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < GW; ++w) t += sh[w];
+  return t;
+}
+
+template <int K>
+__device__ void block_sum_n(double (&v)[K], double* sh /* GW * K */) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) sh[q * GW + wv] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < GW; ++w) t += sh[q * GW + w];
+    v[q] = t;
+  }
+}
+
+__device__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = sh[0];
+  for (int w = 1; w < GW; ++w) t = fmax(t, sh[w]);
+  return t;
+}
+
+// Exclusive prefix sum over threads (in thread order) of one int per thread.
+__device__ int block_exscan(int v, int* sh /* GW + 1 */, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  __syncthreads();
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < GW; ++w) {
+    if (w < wv) base += sh[w];
+    tot += sh[w];
+  }
+  *total = tot;
+  return base + inc - v;
+}
+
+__device__ __forceinline__ uint64_t abs_key(double x) {
+  return (uint64_t)__double_as_longlong(x) & 0x7FFFFFFFFFFFFFFFull;
+}
+__device__ __forceinline__ uint64_t abs_key(float x) {
+  return (uint64_t)(__float_as_uint(x) & 0x7FFFFFFFu);
+}
+
+struct TopkShared {
+  unsigned int hist[256];
+  uint64_t prefix;
+  int need;
+  int scan[GW + 1];
+};
+
+// Select T_kappa of |z| (z of type Z, n entries): returns the threshold key and,
+// through *take_eq, how many entries equal to it are kept (lowest indices).
+template <typename Z>
+__device__ uint64_t topk_threshold(const Z* z, int64_t n, int kappa, TopkShared& sh, int* take_eq) {
+  constexpr int BITS = sizeof(Z) * 8;
+  uint64_t prefix = 0, mask = 0;
+  int need = kappa;
+  for (int d = BITS - 8; d >= 0; d -= 8) {
+    for (int b = threadIdx.x; b < 256; b += GT) sh.hist[b] = 0;
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < n; k += GT) {
+      const uint64_t key = abs_key(z[k]);
+      if ((key & mask) == prefix) atomicAdd(&sh.hist[(key >> d) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int cum = 0, D = 255;
+      for (; D > 0; --D) {
+        if (cum + (int)sh.hist[D] >= need) break;
+        cum += (int)sh.hist[D];
+      }
+      sh.prefix = prefix | ((uint64_t)D << d);
+      sh.need = need - cum;
+    }
+    __syncthreads();
+    prefix = sh.prefix;
+    need = sh.need;
+    mask |= (uint64_t)255 << d;
+    __syncthreads();
+  }
+  *take_eq = need;
+  return prefix;
+}
+
+// Marks T_kappa: calls f(k, selected) for every k in ascending order within each
+// thread's contiguous range; support positions are returned through pos().
+template <typename Z, typename F>
+__device__ void topk_apply(const Z* z, int64_t n, uint64_t thr, int take_eq, TopkShared& sh, F f) {
+  const int64_t chunk = (n + GT - 1) / GT;
+  const int64_t lo = (int64_t)threadIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  int eq = 0;
+  for (int64_t k = lo; k < hi; ++k) eq += (abs_key(z[k]) == thr);
+  int tot;
+  const int eq_base = block_exscan(eq, sh.scan, &tot);
+  int sel = 0, r = eq_base;
+  for (int64_t k = lo; k < hi; ++k) {
+    const uint64_t key = abs_key(z[k]);
+    if (key > thr || (key == thr && r++ < take_eq)) ++sel;
+  }
+  const int sel_base = block_exscan(sel, sh.scan, &tot);
+  int pos = sel_base;
+  r = eq_base;
+  for (int64_t k = lo; k < hi; ++k) {
+    const uint64_t key = abs_key(z[k]);
+    const bool s = key > thr || (key == thr && r++ < take_eq);
+    f(k, s, s ? pos++ : -1);
+  }
+}
+
+__global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
+  __shared__ double shd[GW * (PSECT + 2)];
+  __shared__ TopkShared tks;
+  __shared__ int flag_sh;
+  const int n = a.n, N = a.N;
+  const int tid = threadIdx.x;
+  double* wbar = a.work;
+  double* th = a.work + n;
+  double* c1 = a.work + 2 * (int64_t)n;
+  double* c2 = a.work + 3 * (int64_t)n;
+  double* zprev = a.work + 4 * (int64_t)n;
+  const double aa = N * a.rho_c, rb = a.rho_b;
+  const double v = a.scal[1];
+  if (tid == 0) flag_sh = 0;
+
+  // consensus average and breakpoint data
+  double s1loc = 0.0, thmax = 0.0;
+  bool bad = false;
+  for (int k = tid; k < n; k += GT) {
+    zprev[k] = a.z[k];
+    double sacc = 0.0;
+    for (int i = 0; i < N; ++i) sacc += a.x[(int64_t)i * n + k] + a.u[(int64_t)i * n + k];
+    const double w = sacc / N;
+    bad |= !isfinite(w);
+    wbar[k] = w;
+    const double sg = w > 0.0 ? 1.0 : (w < 0.0 ? -1.0 : 0.0);
+    const double d = 1.0 - sg * a.s[k];
+    const double aw = fabs(w);
+    c1[k] = d * aw;
+    c2[k] = d * d / aa;
+    const double t = d > 0.0 ? aa * aw / d : INFINITY;
+    th[k] = t;
+    s1loc += d * aw;
+    if (t < INFINITY) thmax = fmax(thmax, t);
+  }
+  if (bad) atomicExch(a.status, 1);
+  const double S1all = block_sum(s1loc, shd);
+  const double hi0 = block_max(thmax, shd);
+
+  double theta;
+  if (v - S1all >= 0.0) {
+    theta = 0.0;
+  } else {
+    // psi at the largest breakpoint: only coordinates with d_k = 0 remain, which add 0
+    if (v + hi0 / rb < 0.0) {
+      theta = -v * rb;
+    } else {
+      double lo = 0.0, hi = hi0;
+      for (int round = 0; round < 200; ++round) {
+        double acc[PSECT + 1];
+        double pts[PSECT];
+#pragma unroll
+        for (int p = 0; p < PSECT; ++p) {
+          pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PSECT + 1);
+          acc[p] = 0.0;
+        }
+        acc[PSECT] = 0.0;  // breakpoints strictly inside (lo, hi)
+        for (int k = tid; k < n; k += GT) {
+          const double t = th[k];
+          const double ca = c1[k], cb = c2[k];
+#pragma unroll
+          for (int p = 0; p < PSECT; ++p)
+            if (t > pts[p]) acc[p] += pts[p] * cb - ca;
+          if (t > lo && t < hi) acc[PSECT] += 1.0;
+        }
+        block_sum_n<PSECT + 1>(acc, shd);
+        if (acc[PSECT] == 0.0) break;
+        int p = 0;
+        while (p < PSECT && v + pts[p] / rb + acc[p] < 0.0) ++p;
+        const double nlo = p == 0 ? lo : pts[p - 1];
+        const double nhi = p == PSECT ? hi : pts[p];
+        if (nlo == lo && nhi == hi) break;
+        lo = nlo;
+        hi = nhi;
+      }
+      // exact root on the linear piece whose active set is {theta_k >= hi}
+      double sums[2] = {0.0, 0.0};
+      for (int k = tid; k < n; k += GT) {
+        if (th[k] >= hi) {
+          sums[0] += c1[k];
+          sums[1] += c2[k];
+        }
+      }
+      block_sum_n<2>(sums, shd);
+      theta = (sums[0] - v) / (1.0 / rb + sums[1]);
+      theta = fmin(fmax(theta, lo), hi);
+    }
+  }
+  // z(theta), t = ||z||_1 (theta > 0) or s^T wbar + v (theta = 0)
+  double tl = 0.0;
+  for (int k = tid; k < n; k += GT) {
+    const double w = wbar[k];
+    double zk;
+    if (theta == 0.0) {
+      zk = w;
+      tl += a.s[k] * w;
+    } else {
+      const double y = w + theta * a.s[k] / aa;
+      const double mag = fabs(y) - theta / aa;
+      zk = mag > 0.0 ? (y > 0.0 ? mag : -mag) : 0.0;
+      tl += fabs(zk);
+    }
+    a.z[k] = zk;
+  }
+  double t = block_sum(tl, shd);
+  if (theta == 0.0) t += v;
+  __syncthreads();
+
+  // s-step: T_kappa(z), M_kappa, s
+  int take_eq;
+  const uint64_t thr = topk_threshold<double>(a.z, n, a.kappa, tks, &take_eq);
+  double mk = 0.0;
+  {
+    const int64_t chunk = (n + GT - 1) / GT;
+    const int64_t lo = (int64_t)tid * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    int eq = 0;
+    for (int64_t k = lo; k < hi; ++k) eq += (abs_key(a.z[k]) == thr);
+    int tot;
+    const int eq_base = block_exscan(eq, tks.scan, &tot);
+    int r = eq_base;
+    for (int64_t k = lo; k < hi; ++k) {
+      const uint64_t key = abs_key(a.z[k]);
+      if (key > thr || (key == thr && r++ < take_eq)) mk += fabs(a.z[k]);
+    }
+  }
+  const double Mk = block_sum(mk, shd);
+  const double tau = t - v;
+  const double alpha = Mk > 0.0 ? fmin(fmax(tau / Mk, -1.0), 1.0) : 0.0;
+  double gl = 0.0;
+  topk_apply<double>(a.z, n, thr, take_eq, tks, [&](int64_t k, bool sel, int pos) {
+    const double zk = a.z[k];
+    const double sk = sel ? alpha * (zk > 0.0 ? 1.0 : (zk < 0.0 ? -1.0 : 0.0)) : 0.0;
+    a.s[k] = sk;
+    gl += zk * sk;
+    if (sel && pos < a.kappa) a.support[pos] = (int32_t)k;
+  });
+  const double g = block_sum(gl, shd) - t;
+  const double vn = v + g;
+
+  // u-update and residuals
+  double dz = 0.0;
+  for (int k = tid; k < n; k += GT) {
+    const double d = a.z[k] - zprev[k];
+    dz += d * d;
+  }
+  const double dzs = block_sum(dz, shd);
+  double pr = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double pl = 0.0;
+    for (int k = tid; k < n; k += GT) {
+      const int64_t o = (int64_t)i * n + k;
+      const double d = a.x[o] - a.z[k];
+      pl += d * d;
+      a.u[o] += d;
+    }
+    pr += sqrt(block_sum(pl, shd));
+  }
+  if (tid == 0) {
+    const double dr = sqrt((double)N) * a.rho_c * sqrt(dzs);
+    const double br = fabs(g);
+    const int it = (int)a.scal[5];
+    a.scal[0] = t;
+    a.scal[1] = vn;
+    a.scal[2] = pr;
+    a.scal[3] = dr;
+    a.scal[4] = br;
+    a.scal[5] = (double)(it + 1);
+    if (it < a.hist_cap) {
+      a.hist[3 * (int64_t)it + 0] = pr;
+      a.hist[3 * (int64_t)it + 1] = dr;
+      a.hist[3 * (int64_t)it + 2] = br;
+    }
+    if (!isfinite(t) || !isfinite(vn) || !isfinite(pr)) atomicExch(a.status, 1);
+  }
+}
+
+hipError_t launch_global(const GlobalArgs& a, hipStream_t s) {
+  if (a.C != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(global_kernel, dim3(1), dim3(GT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Z>
+__global__ __launch_bounds__(GT) void topk_kernel(const Z* z, int64_t n, int kappa, int32_t* idx) {
+  __shared__ TopkShared tks;
+  int take_eq;
+  const uint64_t thr = topk_threshold<Z>(z, n, kappa, tks, &take_eq);
+  topk_apply<Z>(z, n, thr, take_eq, tks, [&](int64_t k, bool sel, int pos) {
+    if (sel && pos < kappa) idx[pos] = (int32_t)k;
+  });
+}
+
+hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* idx, double* work,
+                       hipStream_t s) {
+  (void)work;
+  if (f64)
+    hipLaunchKernelGGL(topk_kernel<double>, dim3(1), dim3(GT), 0, s, (const double*)z, n, kappa, idx);
+  else
+    hipLaunchKernelGGL(topk_kernel<float>, dim3(1), dim3(GT), 0, s, (const float*)z, n, kappa, idx);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ input checks
+template <typename T>
+__global__ void check_kernel(const T* p, int64_t count, int* flag) {
+  int bad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite((double)p[k]);
+  if (bad) atomicExch(flag, 1);
+}
+
+__global__ void check_bf16_kernel(const uint16_t* p, int64_t count, int* flag) {
+  int bad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    bad |= ((p[k] & 0x7F80u) == 0x7F80u);
+  if (bad) atomicExch(flag, 1);
+}
+
+hipError_t launch_check(const void* p, int dtype, int64_t count, int* flag, hipStream_t s) {
+  dim3 g(1024), b(256);
+  switch (dtype) {
+    case BCA_F64: hipLaunchKernelGGL(check_kernel<double>, g, b, 0, s, (const double*)p, count, flag); break;
+    case BCA_F32: hipLaunchKernelGGL(check_kernel<float>, g, b, 0, s, (const float*)p, count, flag); break;
+    default: hipLaunchKernelGGL(check_bf16_kernel, g, b, 0, s, (const uint16_t*)p, count, flag); break;
+  }
+  return hipGetLastError();
+}
+
+__global__ void check_labels_kernel(const int32_t* y, int64_t count, int C, int* flag) {
+  int bad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    bad |= (y[k] < 0 || y[k] >= C);
+  if (bad) atomicExch(flag, 1);
+}
+
+hipError_t launch_check_labels(const int32_t* y, int64_t count, int C, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(check_labels_kernel, dim3(256), dim3(256), 0, s, y, count, C, flag);
+  return hipGetLastError();
+}
+
+__global__ void check_signs_kernel(const double* b, int64_t count, int* flag) {
+  int bad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    bad |= !(b[k] == 1.0 || b[k] == -1.0);
+  if (bad) atomicExch(flag, 1);
+}
+
+hipError_t launch_check_signs(const double* b, int64_t count, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(check_signs_kernel, dim3(256), dim3(256), 0, s, b, count, flag);
+  return hipGetLastError();
+}
+
+}  // namespace bca

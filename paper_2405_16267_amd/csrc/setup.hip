@@ -1,0 +1,415 @@
+// One-time setup of the x_ij-step of Sec. 3.1: the ridge problem of every
+// feature block is K_ij x = rhs with
+//     K_ij = rho_l A_ij^T A_ij + (1/(N gamma) + rho_c) I,
+// whose Cholesky factor L_ij is cached.  The triangular solves with L_ij are
+// applied as products with the cached inverse factor W_ij = L_ij^-1 (computed
+// here once in FP64), which turns a sequential substitution into a fully
+// parallel triangular matrix-vector product with the same bytes moved.
+//
+//   gram_kernel      G_ij = A_ij^T A_ij on MFMA (FP64, FP32 or BF16 inputs,
+//                    FP64/FP32 accumulation), lower 64x64 tiles, epilogue
+//                    writes K_ij in FP64.
+//   cholesky_kernel  right-looking blocked Cholesky (32-wide panels) of K_ij in
+//                    FP64, one workgroup per block.
+//   inverse_kernel   W_ij = L_ij^-1 by blocked forward substitution on the
+//                    identity, one workgroup per 64-column block of W.
+//   pack_kernel      packed lower rows (W) and packed lower columns (W^T rows).
+#include "bca_internal.h"
+
+namespace bca {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ Gram
+// MFMA shapes: 16x16 output per instruction, K_STEP contraction rows per
+// instruction.  Operand layout (lane l): A-side element (i = l % 16,
+// k = K_PER_LANE * (l / 16) + e), B-side element (k likewise, j = l % 16).
+// Result element v of lane l is at column l % 16 and row out_row(l, v):
+// 4 (l / 16) + v for the FP32-accumulating shapes, l / 16 + 4 v for FP64
+// (both measured on gfx950).
+template <typename T>
+struct GramMfma;
+
+template <>
+struct GramMfma<float> {
+  using lds_t = float;
+  using acc_t = floatx4;
+  static constexpr int KB = 16;       // rows per LDS chunk
+  static constexpr int K_STEP = 4;    // contraction rows per MFMA
+  static constexpr int K_PER_LANE = 1;
+  static constexpr int PAD = 1;
+  __device__ static lds_t load(const float* p) { return *p; }
+  __device__ static void mma(acc_t& c, const lds_t* a, const lds_t* b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  }
+  __device__ static double out(const acc_t& c, int v) { return (double)c[v]; }
+  __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <>
+struct GramMfma<double> {
+  using lds_t = double;
+  using acc_t = doublex4;
+  static constexpr int KB = 16;
+  static constexpr int K_STEP = 4;
+  static constexpr int K_PER_LANE = 1;
+  static constexpr int PAD = 1;
+  __device__ static lds_t load(const double* p) { return *p; }
+  __device__ static void mma(acc_t& c, const lds_t* a, const lds_t* b) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  }
+  __device__ static double out(const acc_t& c, int v) { return c[v]; }
+  __device__ static int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <>
+struct GramMfma<bf16_t> {
+  using lds_t = __bf16;
+  using acc_t = floatx4;
+  static constexpr int KB = 32;
+  static constexpr int K_STEP = 32;
+  static constexpr int K_PER_LANE = 8;
+  static constexpr int PAD = 8;  // keeps 16-byte alignment of each LDS row
+  __device__ static lds_t load(const bf16_t* p) { return __builtin_bit_cast(__bf16, p->bits); }
+  __device__ static void mma(acc_t& c, const lds_t* a, const lds_t* b) {
+    bf16x8 va = *reinterpret_cast<const bf16x8*>(a);
+    bf16x8 vb = *reinterpret_cast<const bf16x8*>(b);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, c, 0, 0, 0);
+  }
+  __device__ static double out(const acc_t& c, int v) { return (double)c[v]; }
+  __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Lower-triangular tile index t -> (ti, tj), ti >= tj.
+__device__ __forceinline__ void tri_tile(int t, int* ti, int* tj) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *ti = i;
+  *tj = t - i * (i + 1) / 2;
+}
+
+// 64x64 output tile per workgroup of 256 threads; wave w computes the 32x32
+// quadrant (w / 2, w % 2) as 2 x 2 MFMA tiles.  LDS holds the two 64-column
+// panels of a KB-row chunk, transposed (column-major) so each lane's operand
+// run along the contraction index is contiguous.
+template <typename T>
+__global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
+  using MF = GramMfma<T>;
+  using L = typename MF::lds_t;
+  constexpr int KB = MF::KB;
+  constexpr int LS = KB + MF::PAD;
+  __shared__ __attribute__((aligned(16))) L sI[64 * LS];
+  __shared__ __attribute__((aligned(16))) L sJ[64 * LS];
+
+  const int bid = blockIdx.y;
+  const int part = bid / a.M, blk = bid - part * a.M;
+  const int c0 = a.col_off[blk];
+  const int nj = a.col_off[blk + 1] - c0;
+  const int T_ = (nj + 63) / 64;
+  int ti, tj;
+  tri_tile(blockIdx.x, &ti, &tj);
+  if (ti >= T_) return;
+  const int64_t r0 = a.row_off[part];
+  const int64_t m = a.row_off[part + 1] - r0;
+  const T* Ab = reinterpret_cast<const T*>(a.A) + r0 * a.ld + c0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  const bool diag = (ti == tj);
+
+  typename MF::acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = 0;
+
+  for (int64_t k0 = 0; k0 < m; k0 += KB) {
+    // stage: sI[c][k] = A[k0 + k][ti*64 + c], sJ likewise for tj
+    for (int idx = tid; idx < KB * 64; idx += 256) {
+      const int k = idx >> 6, c = idx & 63;
+      const int64_t row = k0 + k;
+      const int ci = ti * 64 + c, cj = tj * 64 + c;
+      L vi = L(0), vj = L(0);
+      if (row < m) {
+        if (ci < nj) vi = MF::load(Ab + row * a.ld + ci);
+        if (!diag && cj < nj) vj = MF::load(Ab + row * a.ld + cj);
+      }
+      sI[c * LS + k] = vi;
+      if (!diag) sJ[c * LS + k] = vj;
+    }
+    __syncthreads();
+    const L* pJ = diag ? sI : sJ;
+#pragma unroll
+    for (int ks = 0; ks < KB; ks += MF::K_STEP) {
+      const int kk = ks + MF::K_PER_LANE * (lane >> 4);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const L* pa = sI + (wr * 32 + x * 16 + (lane & 15)) * LS + kk;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const L* pb = pJ + (wc * 32 + y * 16 + (lane & 15)) * LS + kk;
+          MF::mma(acc[x][y], pa, pb);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* K = a.kbuf + a.kmat_off[bid];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 64 + wr * 32 + x * 16 + MF::out_row(lane, v);
+        const int col = tj * 64 + wc * 32 + y * 16 + (lane & 15);
+        if (row < nj && col < nj && row >= col) {
+          double g = MF::out(acc[x][y], v);
+          K[(int64_t)row * nj + col] = a.rho_l * g + (row == col ? a.shift : 0.0);
+        }
+      }
+}
+
+hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s) {
+  dim3 grid(a.tiles_max * (a.tiles_max + 1) / 2, a.N * a.M);
+  switch (dtype) {
+    case BCA_F64: hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, a); break;
+    case BCA_F32: hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(gram_kernel<bf16_t>, grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Cholesky
+__global__ __launch_bounds__(256) void cholesky_kernel(FactorArgs a) {
+  __shared__ double D[32][33];
+  __shared__ double P0[64][33];
+  __shared__ double P1[64][33];
+  const int bid = blockIdx.x;
+  const int blk = bid % a.M;
+  const int n = a.col_off[blk + 1] - a.col_off[blk];
+  double* K = a.kbuf + a.kmat_off[bid];
+  const int tid = threadIdx.x;
+
+  for (int k0 = 0; k0 < n; k0 += 32) {
+    const int kb = min(32, n - k0);
+    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      const int r = idx >> 5, c = idx & 31;
+      D[r][c] = (r < kb && c <= r) ? K[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    // unblocked factorisation of the diagonal block
+    for (int p = 0; p < kb; ++p) {
+      if (tid == 0) {
+        double d = D[p][p];
+        if (!(d > 0.0) || !isfinite(d)) {
+          atomicExch(a.status, 1);
+          d = 1.0;
+        }
+        D[p][p] = sqrt(d);
+      }
+      __syncthreads();
+      if (tid > p && tid < kb) D[tid][p] /= D[p][p];
+      __syncthreads();
+      for (int idx = tid; idx < 32 * 32; idx += 256) {
+        const int r = idx >> 5, c = idx & 31;
+        if (c > p && r >= c && r < kb) D[r][c] -= D[r][p] * D[c][p];
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      const int r = idx >> 5, c = idx & 31;
+      if (r < kb && c <= r) K[(int64_t)(k0 + r) * n + k0 + c] = D[r][c];
+    }
+    // panel below the diagonal block: L[r, k0:k0+kb] = K[r, k0:k0+kb] D^-T
+    const int k1 = k0 + kb;
+    for (int r = k1 + tid; r < n; r += 256) {
+      double x[32];
+      double* row = K + (int64_t)r * n + k0;
+#pragma unroll
+      for (int p = 0; p < 32; ++p) x[p] = (p < kb) ? row[p] : 0.0;
+#pragma unroll
+      for (int p = 0; p < 32; ++p) {
+        if (p < kb) {
+          double v = x[p];
+#pragma unroll
+          for (int q = 0; q < 32; ++q)
+            if (q < p) v -= x[q] * D[p][q];
+          x[p] = v / D[p][p];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 32; ++p)
+        if (p < kb) row[p] = x[p];
+    }
+    __syncthreads();
+    // trailing update K[r, c] -= sum_p L[r, p] L[c, p], k1 <= c <= r < n
+    const int nt = (n - k1 + 63) / 64;
+    const int ty = tid >> 4, tx = tid & 15;
+    for (int t = 0; t < nt * (nt + 1) / 2; ++t) {
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      const int tj = t - ti * (ti + 1) / 2;
+      for (int idx = tid; idx < 64 * 32; idx += 256) {
+        const int r = idx >> 5, p = idx & 31;
+        const int gi = k1 + ti * 64 + r, gj = k1 + tj * 64 + r;
+        P0[r][p] = (gi < n && p < kb) ? K[(int64_t)gi * n + k0 + p] : 0.0;
+        P1[r][p] = (gj < n && p < kb) ? K[(int64_t)gj * n + k0 + p] : 0.0;
+      }
+      __syncthreads();
+      double acc[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+      for (int p = 0; p < kb; ++p) {
+        double li[4], lj[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) li[x] = P0[ty + 16 * x][p];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) lj[y] = P1[tx + 16 * y][p];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * lj[y];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int gi = k1 + ti * 64 + ty + 16 * x, gj = k1 + tj * 64 + tx + 16 * y;
+          if (gi < n && gj <= gi) K[(int64_t)gi * n + gj] -= acc[x][y];
+        }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_cholesky(const FactorArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(cholesky_kernel, dim3(a.N * a.M), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ inverse factor
+// Workgroup (block, kc) computes columns [64 kc, 64 kc + 64) of W = L^-1:
+//   W[ib, kc] = L[ib, ib]^-1 (delta(ib, kc) I - sum_{kc <= pb < ib} L[ib, pb] W[pb, kc]).
+__global__ __launch_bounds__(256) void inverse_kernel(FactorArgs a) {
+  // LDS: the GEMM chunks (S0: 64 x 17, S1: 16 x 64) and the diagonal block of L
+  // (64 x 64) share one buffer; Tt holds the 64 x 64 tile being solved.
+  __shared__ double smem[64 * 64];
+  __shared__ double Tt[64 * 64];
+  double* S0 = smem;            // [64][17]
+  double* S1 = smem + 64 * 17;  // [16][64]
+  double* Ld = smem;            // [64][64]
+  const int bid = blockIdx.x;
+  const int blk = bid % a.M;
+  const int n = a.col_off[blk + 1] - a.col_off[blk];
+  const int kc = blockIdx.y;
+  if (kc * 64 >= n) return;
+  const double* L = a.kbuf + a.kmat_off[bid];
+  double* W = a.wbuf + a.kmat_off[bid];
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int nb = (n + 63) / 64;
+  const int c0 = kc * 64;
+
+  for (int ib = kc; ib < nb; ++ib) {
+    const int R0 = ib * 64;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    // sum over p in [c0, R0) of L[R0 + r, p] W[p, c0 + c]
+    for (int p0 = c0; p0 < R0; p0 += 16) {
+      for (int idx = tid; idx < 64 * 16; idx += 256) {
+        const int r = idx >> 4, p = idx & 15;
+        const int gr = R0 + r, gp = p0 + p;
+        S0[r * 17 + p] = (gr < n && gp < R0) ? L[(int64_t)gr * n + gp] : 0.0;
+      }
+      for (int idx = tid; idx < 16 * 64; idx += 256) {
+        const int p = idx >> 6, c = idx & 63;
+        const int gp = p0 + p, gc = c0 + c;
+        S1[p * 64 + c] = (gp < R0 && gc < n) ? W[(int64_t)gp * n + gc] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int p = 0; p < 16; ++p) {
+        double li[4], wj[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) li[x] = S0[(ty + 16 * x) * 17 + p];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) wj[y] = S1[p * 64 + tx + 16 * y];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * wj[y];
+      }
+      __syncthreads();
+    }
+    // right-hand side tile: delta I - acc; diagonal block of L into LDS
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int r = ty + 16 * x, c = tx + 16 * y;
+        Tt[r * 64 + c] = ((ib == kc && r == c) ? 1.0 : 0.0) - acc[x][y];
+      }
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      const int r = idx >> 6, q = idx & 63;
+      Ld[idx] = (R0 + r < n && q <= r) ? L[(int64_t)(R0 + r) * n + R0 + q] : (q == r ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // forward substitution with L[ib, ib], one thread per column
+    if (tid < 64) {
+      const int c = tid;
+      for (int r = 0; r < 64; ++r) {
+        double v = Tt[r * 64 + c];
+        for (int q = 0; q < r; ++q) v -= Ld[r * 64 + q] * Tt[q * 64 + c];
+        Tt[r * 64 + c] = v / Ld[r * 64 + r];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+      const int r = idx >> 6, c = idx & 63;
+      if (R0 + r < n && c0 + c < n) W[(int64_t)(R0 + r) * n + c0 + c] = Tt[idx];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_inverse(const FactorArgs& a, hipStream_t s) {
+  dim3 grid(a.N * a.M, (a.nj_max + 63) / 64);
+  hipLaunchKernelGGL(inverse_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ packing
+// wr: row r of W (columns 0..r) at r (r + 1) / 2.
+// wc: column c of W (rows c..n-1) at c n - c (c - 1) / 2.
+__global__ __launch_bounds__(256) void pack_kernel(FactorArgs a) {
+  const int bid = blockIdx.y;
+  const int blk = bid % a.M;
+  const int n = a.col_off[blk + 1] - a.col_off[blk];
+  const double* W = a.wbuf + a.kmat_off[bid];
+  double* wr = a.wr + a.fac_off[bid];
+  double* wc = a.wc + a.fac_off[bid];
+  for (int r = blockIdx.x; r < n; r += gridDim.x) {
+    for (int c = threadIdx.x; c <= r; c += 256) {
+      const double v = W[(int64_t)r * n + c];
+      wr[(int64_t)r * (r + 1) / 2 + c] = v;
+      wc[(int64_t)c * n - (int64_t)c * (c - 1) / 2 + (r - c)] = v;
+    }
+  }
+}
+
+hipError_t launch_pack(const FactorArgs& a, hipStream_t s) {
+  dim3 grid(256, a.N * a.M);
+  hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace bca

@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="slogr_8x50000x5000_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the partitions of this build live in one GPU's "
@@ -97,9 +99,19 @@ def main():
 
     import numpy as np
     import torch
-    import paper_2405_16267_amd as bca
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4}), flush=True)
+        return
+    import paper_2405_16267_amd as bca
+
     t = time.perf_counter()
     w = workload(args.workload)
     log("generated %s in %.1f s" % (w.name, time.perf_counter() - t))

@@ -170,6 +170,7 @@ StreamArgs stream_args(bca_problem P, int mode) {
   a.N = P->N;
   a.Gp = P->Gp;
   a.nvec = P->nvec;
+  a.n = P->n;
   a.M = P->M;
   a.C = P->C;
   a.loss = P->p.loss;
@@ -281,10 +282,11 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   *out = nullptr;
   const bca_params& p = *prm;
   if (p.loss < 0 || p.loss > 2) return fail(BCA_E_INVALID, "unknown loss %d", p.loss);
-  if (p.loss == BCA_LOSS_SOFTMAX) return fail(BCA_E_INVALID, "softmax loss is not available in this build");
-  const int C = 1;
+  const int C = p.loss == BCA_LOSS_SOFTMAX ? p.n_classes : 1;
   if (p.loss != BCA_LOSS_SOFTMAX && p.n_classes != 1 && p.n_classes != 0)
     return fail(BCA_E_INVALID, "n_classes must be 1 for this loss");
+  if (p.loss == BCA_LOSS_SOFTMAX && (C < 2 || !mc_supported(p.n_features, C)))
+    return fail(BCA_E_INVALID, "softmax needs 2 <= n_classes <= 16 and n_features <= 2048");
   if (p.n_features < 1) return fail(BCA_E_INVALID, "n_features must be >= 1");
   if (p.n_partitions < 1) return fail(BCA_E_INVALID, "n_partitions must be >= 1");
   if (p.n_blocks < 1 || p.n_blocks > p.n_features) return fail(BCA_E_INVALID, "need 1 <= n_blocks <= n_features");
@@ -363,7 +365,10 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
       P->A = a;
     }
   }
-  if (rc == BCA_OK) chk(dalloc(P, &P->b, P->m_total));
+  if (rc == BCA_OK) {
+    if (p.loss == BCA_LOSS_SOFTMAX) chk(dalloc(P, &P->y, P->m_total));
+    else chk(dalloc(P, &P->b, P->m_total));
+  }
   if (rc == BCA_OK) chk(dalloc(P, &P->omega, (size_t)P->m_total * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->nu, (size_t)P->m_total * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->x, (size_t)P->N * P->n * C));
@@ -383,7 +388,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->s, (size_t)P->n));
   if (rc == BCA_OK) chk(dalloc(P, &P->scal, 8));
   if (rc == BCA_OK) chk(dalloc(P, &P->hist, (size_t)p.max_iters * 3));
-  if (rc == BCA_OK) chk(dalloc(P, &P->work, (size_t)P->n * 6));
+  if (rc == BCA_OK) chk(dalloc(P, &P->work, (size_t)P->n * (2 * C + 5)));
   if (rc == BCA_OK) chk(dalloc(P, &P->support, (size_t)P->kappa));
   if (rc == BCA_OK) chk(dalloc(P, &P->status, 4));
   if (rc == BCA_OK) chk(dalloc(P, &P->gpart, (size_t)P->N * P->Gp * P->ld * C));
@@ -432,14 +437,19 @@ int bca_set_data(bca_problem P, int32_t part, const void* A, int64_t ld, const v
   const hipMemcpyKind kind = mem == BCA_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   char* dstA = reinterpret_cast<char*>(P->A) + (size_t)P->row_off[part] * P->ld * es;
   HIP_TRY(hipMemcpy2DAsync(dstA, P->ld * es, A, ld * es, P->n * es, m, kind, P->stream));
-  HIP_TRY(hipMemcpyAsync(P->b + P->row_off[part], b, m * sizeof(double), kind, P->stream));
-  HIP_TRY(hipMemsetAsync(P->status + 1, 0, sizeof(int), P->stream));
+  const bool softmax = P->p.loss == BCA_LOSS_SOFTMAX;
+  if (softmax)
+    HIP_TRY(hipMemcpyAsync(P->y + P->row_off[part], b, m * sizeof(int32_t), kind, P->stream));
+  else
+    HIP_TRY(hipMemcpyAsync(P->b + P->row_off[part], b, m * sizeof(double), kind, P->stream));
+  HIP_TRY(hipMemsetAsync(P->status + 1, 0, 2 * sizeof(int), P->stream));
   TRY(launch_ok(launch_check(dstA, P->dtype, m * P->ld, P->status + 1, P->stream), "check"));
-  TRY(launch_ok(launch_check(P->b + P->row_off[part], BCA_F64, m, P->status + 1, P->stream), "check"));
-  if (P->p.loss == BCA_LOSS_LOGISTIC) {
-    HIP_TRY(hipMemsetAsync(P->status + 2, 0, sizeof(int), P->stream));
+  if (!softmax)
+    TRY(launch_ok(launch_check(P->b + P->row_off[part], BCA_F64, m, P->status + 1, P->stream), "check"));
+  if (P->p.loss == BCA_LOSS_LOGISTIC)
     TRY(launch_ok(launch_check_signs(P->b + P->row_off[part], m, P->status + 2, P->stream), "check"));
-  }
+  if (softmax)
+    TRY(launch_ok(launch_check_labels(P->y + P->row_off[part], m, P->C, P->status + 2, P->stream), "check"));
   int flags[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(flags, P->status + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
@@ -447,9 +457,10 @@ int bca_set_data(bca_problem P, int32_t part, const void* A, int64_t ld, const v
     P->loaded[part] = 0;
     return fail(BCA_E_NONFINITE, "partition %d: NaN/Inf in A or b", part);
   }
-  if (P->p.loss == BCA_LOSS_LOGISTIC && flags[1]) {
+  if (flags[1]) {
     P->loaded[part] = 0;
-    return fail(BCA_E_INVALID, "partition %d: logistic labels must be -1 or +1", part);
+    return fail(BCA_E_INVALID, softmax ? "partition %d: class ids must be in [0, n_classes)"
+                                       : "partition %d: logistic labels must be -1 or +1", part);
   }
   P->loaded[part] = 1;
   return BCA_OK;
@@ -567,13 +578,9 @@ int bca_solve(bca_problem P, int32_t* iters_done, int32_t* converged) {
 int bca_get_support(bca_problem P, int32_t* idx, int32_t* count) {
   if (!P || !idx) return fail(BCA_E_INVALID, "null argument");
   if (!P->finalized) return fail(BCA_E_STATE, "no solution before finalize");
-  if (P->iter == 0) {
-    // T_kappa of the zero vector: the first kappa indices
-    for (int k = 0; k < P->kappa; ++k) idx[k] = k;
-  } else {
-    HIP_TRY(hipMemcpyAsync(idx, P->support, P->kappa * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
-  }
+  TRY(launch_ok(launch_support(P->z, P->n, P->C, P->kappa, P->support, P->work, P->stream), "support"));
+  HIP_TRY(hipMemcpyAsync(idx, P->support, P->kappa * sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
   if (count) *count = P->kappa;
   return BCA_OK;
 }
@@ -649,6 +656,7 @@ int bca_get_objective(bca_problem P, double* f) {
   o.N = P->N;
   o.Gp = P->Gp;
   o.nvec = P->nvec;
+  o.n = P->n;
   o.C = P->C;
   o.loss = P->p.loss;
   TRY(launch_ok(launch_objective(o, P->dtype, P->stream), "objective"));
@@ -777,10 +785,6 @@ int bca_set_state(bca_problem P, const void* buf, size_t bytes) {
   HIP_TRY(hipMemcpyAsync(P->hist, d, (size_t)P->p.max_iters * 3 * 8, hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->iter = h.iter;
-  // support of the restored z
-  if (P->iter > 0) {
-    TRY(launch_ok(launch_topk(P->z, 1, P->n, P->kappa, P->support, P->work, P->stream), "topk"));
-  }
   P->need_prime = true;
   return BCA_OK;
 }

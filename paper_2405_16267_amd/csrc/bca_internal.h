@@ -86,7 +86,7 @@ struct StreamArgs {
   double* nu;              // m_total x C
   const void* xs;          // N x ld x C streaming copy of x (FP64 or FP32)
   double* gpart;           // N x Gp x ld x C partial sums of A^T e
-  int N, Gp, nvec, M, C, loss;
+  int N, Gp, nvec, n, M, C, loss;
   double inv_M, rho_l;
   int mode;                // 0: inner iteration; 1: prime (e from stored state, no prox)
 };
@@ -100,7 +100,7 @@ struct ObjArgs {
   const int32_t* y;
   const void* xs;          // x_hat streaming copy, ld x C (shared by all partitions)
   double* partial;         // N x Gp
-  int N, Gp, nvec, C, loss;
+  int N, Gp, nvec, n, C, loss;
 };
 
 struct Problem;  // host-side problem (bca_api.hip)
@@ -108,6 +108,10 @@ struct Problem;  // host-side problem (bca_api.hip)
 // Launchers (host side).  Each returns hipSuccess or the launch error.
 hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s);
 hipError_t launch_objective(const ObjArgs& a, int dtype, hipStream_t s);
+// C > 1 (softmax) forms of the two passes (stream_mc.hip)
+bool mc_supported(int n, int C);
+hipError_t launch_stream_mc(const StreamArgs& a, int dtype, hipStream_t s);
+hipError_t launch_objective_mc(const ObjArgs& a, int dtype, hipStream_t s);
 int stream_occupancy_workgroups(int dtype, int nvec, int C);   // resident workgroups per CU
 
 struct GramArgs {
@@ -166,7 +170,7 @@ struct GlobalArgs {
   double* scal;            // [0] t, [1] v, [2] pr, [3] dr, [4] br, [5] iter (as double)
   double* hist;            // hist_cap x 3
   int32_t* support;        // kappa
-  double* work;            // scratch: 6 n doubles
+  double* work;            // scratch: (2 C + 5) n doubles
   int* status;             // nonzero on NaN/Inf
   int N, n, C, kappa, hist_cap;
   double rho_c, rho_b;
@@ -175,6 +179,9 @@ hipError_t launch_global(const GlobalArgs& a, hipStream_t s);
 
 hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* idx, double* work,
                        hipStream_t s);
+// T_kappa of z (rows by Euclidean norm when C > 1); work holds n doubles.
+hipError_t launch_support(const double* z, int n, int C, int kappa, int32_t* idx, double* work,
+                          hipStream_t s);
 
 // Non-finite scan of a device buffer of `count` elements (dtype BCA_*), plus an
 // optional label range check; sets *flag nonzero if anything is off.

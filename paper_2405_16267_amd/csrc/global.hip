@@ -164,28 +164,37 @@ __device__ void topk_apply(const Z* z, int64_t n, uint64_t thr, int take_eq, Top
 __global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
   __shared__ double shd[GW * (PSECT + 2)];
   __shared__ TopkShared tks;
-  __shared__ int flag_sh;
-  const int n = a.n, N = a.N;
+  const int n = a.n, N = a.N, C = a.C;
+  const int64_t nc = (int64_t)n * C;
   const int tid = threadIdx.x;
-  double* wbar = a.work;
-  double* th = a.work + n;
-  double* c1 = a.work + 2 * (int64_t)n;
-  double* c2 = a.work + 3 * (int64_t)n;
-  double* zprev = a.work + 4 * (int64_t)n;
+  double* wbar = a.work;              // n x C
+  double* zprev = a.work + nc;        // n x C
+  double* rv = a.work + 2 * nc;       // per row: wbar (C = 1) or ||wbar_k|| (C > 1)
+  double* th = rv + n;
+  double* c1 = th + n;
+  double* c2 = c1 + n;
+  double* rz = c2 + n;                // per row of z: z_k (C = 1) or ||z_k|| (C > 1)
   const double aa = N * a.rho_c, rb = a.rho_b;
   const double v = a.scal[1];
-  if (tid == 0) flag_sh = 0;
 
-  // consensus average and breakpoint data
+  // consensus average and breakpoint data of the vector (z,t) problem
   double s1loc = 0.0, thmax = 0.0;
   bool bad = false;
   for (int k = tid; k < n; k += GT) {
-    zprev[k] = a.z[k];
-    double sacc = 0.0;
-    for (int i = 0; i < N; ++i) sacc += a.x[(int64_t)i * n + k] + a.u[(int64_t)i * n + k];
-    const double w = sacc / N;
+    double nrm2 = 0.0, w1 = 0.0;
+    for (int c = 0; c < C; ++c) {
+      const int64_t e = (int64_t)k * C + c;
+      zprev[e] = a.z[e];
+      double sacc = 0.0;
+      for (int i = 0; i < N; ++i) sacc += a.x[(int64_t)i * nc + e] + a.u[(int64_t)i * nc + e];
+      const double w = sacc / N;
+      wbar[e] = w;
+      nrm2 += w * w;
+      w1 = w;
+    }
+    const double w = C == 1 ? w1 : sqrt(nrm2);
     bad |= !isfinite(w);
-    wbar[k] = w;
+    rv[k] = w;
     const double sg = w > 0.0 ? 1.0 : (w < 0.0 ? -1.0 : 0.0);
     const double d = 1.0 - sg * a.s[k];
     const double aw = fabs(w);
@@ -203,56 +212,54 @@ __global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
   double theta;
   if (v - S1all >= 0.0) {
     theta = 0.0;
+  } else if (v + hi0 / rb < 0.0) {
+    // root beyond the last breakpoint: only coordinates with d_k = 0 remain, adding 0
+    theta = -v * rb;
   } else {
-    // psi at the largest breakpoint: only coordinates with d_k = 0 remain, which add 0
-    if (v + hi0 / rb < 0.0) {
-      theta = -v * rb;
-    } else {
-      double lo = 0.0, hi = hi0;
-      for (int round = 0; round < 200; ++round) {
-        double acc[PSECT + 1];
-        double pts[PSECT];
+    double lo = 0.0, hi = hi0;
+    for (int round = 0; round < 200; ++round) {
+      double acc[PSECT + 1];
+      double pts[PSECT];
 #pragma unroll
-        for (int p = 0; p < PSECT; ++p) {
-          pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PSECT + 1);
-          acc[p] = 0.0;
-        }
-        acc[PSECT] = 0.0;  // breakpoints strictly inside (lo, hi)
-        for (int k = tid; k < n; k += GT) {
-          const double t = th[k];
-          const double ca = c1[k], cb = c2[k];
-#pragma unroll
-          for (int p = 0; p < PSECT; ++p)
-            if (t > pts[p]) acc[p] += pts[p] * cb - ca;
-          if (t > lo && t < hi) acc[PSECT] += 1.0;
-        }
-        block_sum_n<PSECT + 1>(acc, shd);
-        if (acc[PSECT] == 0.0) break;
-        int p = 0;
-        while (p < PSECT && v + pts[p] / rb + acc[p] < 0.0) ++p;
-        const double nlo = p == 0 ? lo : pts[p - 1];
-        const double nhi = p == PSECT ? hi : pts[p];
-        if (nlo == lo && nhi == hi) break;
-        lo = nlo;
-        hi = nhi;
+      for (int p = 0; p < PSECT; ++p) {
+        pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PSECT + 1);
+        acc[p] = 0.0;
       }
-      // exact root on the linear piece whose active set is {theta_k >= hi}
-      double sums[2] = {0.0, 0.0};
+      acc[PSECT] = 0.0;  // breakpoints strictly inside (lo, hi)
       for (int k = tid; k < n; k += GT) {
-        if (th[k] >= hi) {
-          sums[0] += c1[k];
-          sums[1] += c2[k];
-        }
+        const double t = th[k];
+        const double ca = c1[k], cb = c2[k];
+#pragma unroll
+        for (int p = 0; p < PSECT; ++p)
+          if (t > pts[p]) acc[p] += pts[p] * cb - ca;
+        if (t > lo && t < hi) acc[PSECT] += 1.0;
       }
-      block_sum_n<2>(sums, shd);
-      theta = (sums[0] - v) / (1.0 / rb + sums[1]);
-      theta = fmin(fmax(theta, lo), hi);
+      block_sum_n<PSECT + 1>(acc, shd);
+      if (acc[PSECT] == 0.0) break;
+      int p = 0;
+      while (p < PSECT && v + pts[p] / rb + acc[p] < 0.0) ++p;
+      const double nlo = p == 0 ? lo : pts[p - 1];
+      const double nhi = p == PSECT ? hi : pts[p];
+      if (nlo == lo && nhi == hi) break;
+      lo = nlo;
+      hi = nhi;
     }
+    // exact root on the linear piece whose active set is {theta_k >= hi}
+    double sums[2] = {0.0, 0.0};
+    for (int k = tid; k < n; k += GT) {
+      if (th[k] >= hi) {
+        sums[0] += c1[k];
+        sums[1] += c2[k];
+      }
+    }
+    block_sum_n<2>(sums, shd);
+    theta = (sums[0] - v) / (1.0 / rb + sums[1]);
+    theta = fmin(fmax(theta, lo), hi);
   }
-  // z(theta), t = ||z||_1 (theta > 0) or s^T wbar + v (theta = 0)
+  // z(theta) per row; rows of the matrix variable are scaled copies of wbar_k
   double tl = 0.0;
   for (int k = tid; k < n; k += GT) {
-    const double w = wbar[k];
+    const double w = rv[k];
     double zk;
     if (theta == 0.0) {
       zk = w;
@@ -263,36 +270,42 @@ __global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
       zk = mag > 0.0 ? (y > 0.0 ? mag : -mag) : 0.0;
       tl += fabs(zk);
     }
-    a.z[k] = zk;
+    rz[k] = zk;
+    if (C == 1) {
+      a.z[k] = zk;
+    } else {
+      const double sc = w > 0.0 ? zk / w : 0.0;
+      for (int c = 0; c < C; ++c) a.z[(int64_t)k * C + c] = wbar[(int64_t)k * C + c] * sc;
+    }
   }
   double t = block_sum(tl, shd);
   if (theta == 0.0) t += v;
   __syncthreads();
 
-  // s-step: T_kappa(z), M_kappa, s
+  // s-step on the row values: T_kappa, M_kappa, s
   int take_eq;
-  const uint64_t thr = topk_threshold<double>(a.z, n, a.kappa, tks, &take_eq);
+  const uint64_t thr = topk_threshold<double>(rz, n, a.kappa, tks, &take_eq);
   double mk = 0.0;
   {
     const int64_t chunk = (n + GT - 1) / GT;
     const int64_t lo = (int64_t)tid * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     int eq = 0;
-    for (int64_t k = lo; k < hi; ++k) eq += (abs_key(a.z[k]) == thr);
+    for (int64_t k = lo; k < hi; ++k) eq += (abs_key(rz[k]) == thr);
     int tot;
     const int eq_base = block_exscan(eq, tks.scan, &tot);
     int r = eq_base;
     for (int64_t k = lo; k < hi; ++k) {
-      const uint64_t key = abs_key(a.z[k]);
-      if (key > thr || (key == thr && r++ < take_eq)) mk += fabs(a.z[k]);
+      const uint64_t key = abs_key(rz[k]);
+      if (key > thr || (key == thr && r++ < take_eq)) mk += fabs(rz[k]);
     }
   }
   const double Mk = block_sum(mk, shd);
   const double tau = t - v;
   const double alpha = Mk > 0.0 ? fmin(fmax(tau / Mk, -1.0), 1.0) : 0.0;
   double gl = 0.0;
-  topk_apply<double>(a.z, n, thr, take_eq, tks, [&](int64_t k, bool sel, int pos) {
-    const double zk = a.z[k];
+  topk_apply<double>(rz, n, thr, take_eq, tks, [&](int64_t k, bool sel, int pos) {
+    const double zk = rz[k];
     const double sk = sel ? alpha * (zk > 0.0 ? 1.0 : (zk < 0.0 ? -1.0 : 0.0)) : 0.0;
     a.s[k] = sk;
     gl += zk * sk;
@@ -301,19 +314,19 @@ __global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
   const double g = block_sum(gl, shd) - t;
   const double vn = v + g;
 
-  // u-update and residuals
+  // u-update and residuals (Frobenius norms for C > 1)
   double dz = 0.0;
-  for (int k = tid; k < n; k += GT) {
-    const double d = a.z[k] - zprev[k];
+  for (int64_t e = tid; e < nc; e += GT) {
+    const double d = a.z[e] - zprev[e];
     dz += d * d;
   }
   const double dzs = block_sum(dz, shd);
   double pr = 0.0;
   for (int i = 0; i < N; ++i) {
     double pl = 0.0;
-    for (int k = tid; k < n; k += GT) {
-      const int64_t o = (int64_t)i * n + k;
-      const double d = a.x[o] - a.z[k];
+    for (int64_t e = tid; e < nc; e += GT) {
+      const int64_t o = (int64_t)i * nc + e;
+      const double d = a.x[o] - a.z[e];
       pl += d * d;
       a.u[o] += d;
     }
@@ -339,7 +352,7 @@ __global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
 }
 
 hipError_t launch_global(const GlobalArgs& a, hipStream_t s) {
-  if (a.C != 1) return hipErrorInvalidValue;
+  if (a.C < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(global_kernel, dim3(1), dim3(GT), 0, s, a);
   return hipGetLastError();
 }
@@ -361,6 +374,33 @@ hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* id
     hipLaunchKernelGGL(topk_kernel<double>, dim3(1), dim3(GT), 0, s, (const double*)z, n, kappa, idx);
   else
     hipLaunchKernelGGL(topk_kernel<float>, dim3(1), dim3(GT), 0, s, (const float*)z, n, kappa, idx);
+  return hipGetLastError();
+}
+
+// T_kappa of the current z: row values (z_k, or ||z_k|| for C > 1) then the radix select.
+__global__ __launch_bounds__(GT) void support_kernel(const double* z, int n, int C, int kappa,
+                                                     int32_t* idx, double* rv) {
+  __shared__ TopkShared tks;
+  for (int k = threadIdx.x; k < n; k += GT) {
+    if (C == 1) {
+      rv[k] = z[k];
+    } else {
+      double s = 0.0;
+      for (int c = 0; c < C; ++c) s += z[(int64_t)k * C + c] * z[(int64_t)k * C + c];
+      rv[k] = sqrt(s);
+    }
+  }
+  __syncthreads();
+  int take_eq;
+  const uint64_t thr = topk_threshold<double>(rv, n, kappa, tks, &take_eq);
+  topk_apply<double>(rv, n, thr, take_eq, tks, [&](int64_t k, bool sel, int pos) {
+    if (sel && pos < kappa) idx[pos] = (int32_t)k;
+  });
+}
+
+hipError_t launch_support(const double* z, int n, int C, int kappa, int32_t* idx, double* work,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(support_kernel, dim3(1), dim3(GT), 0, s, z, n, C, kappa, idx, work);
   return hipGetLastError();
 }
 

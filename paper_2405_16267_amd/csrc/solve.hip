@@ -18,30 +18,34 @@
 namespace bca {
 
 __global__ __launch_bounds__(256) void reduce_rhs_kernel(SolveArgs a) {
+  // one thread per element (k, c) of the n x C block vector, flat index k C + c
   const int part = blockIdx.y;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= a.n) return;
-  const double* g = a.gpart + (int64_t)part * a.Gp * a.ld + k;
+  const int64_t nc = (int64_t)a.n * a.C;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= nc) return;
+  const int64_t stride = a.ld * a.C;
+  const double* g = a.gpart + (int64_t)part * a.Gp * stride + k;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int w = 0;
   for (; w + 4 <= a.Gp; w += 4) {
-    s0 += g[(int64_t)w * a.ld];
-    s1 += g[(int64_t)(w + 1) * a.ld];
-    s2 += g[(int64_t)(w + 2) * a.ld];
-    s3 += g[(int64_t)(w + 3) * a.ld];
+    s0 += g[(int64_t)w * stride];
+    s1 += g[(int64_t)(w + 1) * stride];
+    s2 += g[(int64_t)(w + 2) * stride];
+    s3 += g[(int64_t)(w + 3) * stride];
   }
-  for (; w < a.Gp; ++w) s0 += g[(int64_t)w * a.ld];
+  for (; w < a.Gp; ++w) s0 += g[(int64_t)w * stride];
   const double ate = (s0 + s1) + (s2 + s3);
-  const int64_t o = (int64_t)part * a.n + k;
+  const int64_t o = (int64_t)part * nc + k;
   a.rhs[o] = a.rho_l * ate + a.rho_c * (a.z[k] - a.u[o]) - a.shift * a.x[o];
 }
 
 // One wavefront per pair of rows (q, nj - 1 - q) of a triangular block, so every
-// wave reads about nj + 1 factor entries.
+// wave reads about nj + 1 factor entries; each factor entry is applied to all C
+// right-hand sides (the block vectors are n x C, feature-major).
 //   TRANS = 0: row r of W, entries W[r, 0..r] at wr + r (r + 1) / 2, times in[0..r].
 //   TRANS = 1: row c of W^T, entries W[c..nj-1, c] at wc + c nj - c (c - 1) / 2,
 //              times in[c..nj-1]; the result is added to x.
-template <int TRANS>
+template <int TRANS, int CC>
 __global__ __launch_bounds__(256) void trmv_kernel(SolveArgs a, const double* in, double* out) {
   const int bid = blockIdx.y;
   const int part = bid / a.M, blk = bid - part * a.M;
@@ -51,8 +55,9 @@ __global__ __launch_bounds__(256) void trmv_kernel(SolveArgs a, const double* in
   const int lane = threadIdx.x & 63;
   const int pr = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (pr >= pairs) return;
+  const int C = CC == 1 ? 1 : a.C;
   const double* F = (TRANS ? a.wc : a.wr) + a.fac_off[bid];
-  const double* v = in + (int64_t)part * a.n + c0;
+  const double* v = in + ((int64_t)part * a.n + c0) * C;
   for (int h = 0; h < 2; ++h) {
     const int r = h == 0 ? pr : nj - 1 - pr;
     if (h == 1 && r == pr) break;
@@ -68,42 +73,68 @@ __global__ __launch_bounds__(256) void trmv_kernel(SolveArgs a, const double* in
       len = nj - r;
     }
     const double* f = F + off;
-    const double* vv = v + st;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int e = lane;
-    for (; e + 192 < len; e += 256) {
-      s0 += f[e] * vv[e];
-      s1 += f[e + 64] * vv[e + 64];
-      s2 += f[e + 128] * vv[e + 128];
-      s3 += f[e + 192] * vv[e + 192];
+    double tot[CC];
+    if (CC == 1) {
+      const double* vv = v + st;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int e = lane;
+      for (; e + 192 < len; e += 256) {
+        s0 += f[e] * vv[e];
+        s1 += f[e + 64] * vv[e + 64];
+        s2 += f[e + 128] * vv[e + 128];
+        s3 += f[e + 192] * vv[e + 192];
+      }
+      for (; e < len; e += 64) s0 += f[e] * vv[e];
+      tot[0] = wave_sum((s0 + s1) + (s2 + s3));
+    } else {
+      double sc[CC];
+#pragma unroll
+      for (int c = 0; c < CC; ++c) sc[c] = 0.0;
+      for (int e = lane; e < len; e += 64) {
+        const double fe = f[e];
+        const double* vv = v + (int64_t)(st + e) * C;
+#pragma unroll
+        for (int c = 0; c < CC; ++c)
+          if (c < C) sc[c] += fe * vv[c];
+      }
+#pragma unroll
+      for (int c = 0; c < CC; ++c) tot[c] = wave_sum(sc[c]);
     }
-    for (; e < len; e += 64) s0 += f[e] * vv[e];
-    const double tot = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) {
-      const int64_t o = (int64_t)part * a.n + c0 + r;
-      if (!TRANS) {
-        out[o] = tot;
-      } else {
-        const double xn = a.x[o] + tot;
-        a.xw[o] = xn;
-        const int64_t so = (int64_t)part * a.ld + c0 + r;
-        if (a.xs_f64)
-          reinterpret_cast<double*>(a.xs)[so] = xn;
-        else
-          reinterpret_cast<float*>(a.xs)[so] = (float)xn;
+      for (int c = 0; c < C; ++c) {
+        const int64_t o = ((int64_t)part * a.n + c0 + r) * C + c;
+        if (!TRANS) {
+          out[o] = tot[c];
+        } else {
+          const double xn = a.x[o] + tot[c];
+          a.xw[o] = xn;
+          const int64_t so = (int64_t)part * a.ld * C + (int64_t)(c0 + r) * C + c;
+          if (a.xs_f64)
+            reinterpret_cast<double*>(a.xs)[so] = xn;
+          else
+            reinterpret_cast<float*>(a.xs)[so] = (float)xn;
+        }
       }
     }
   }
 }
 
-hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
-  if (a.C != 1) return hipErrorInvalidValue;
-  dim3 g1((a.n + 255) / 256, a.N);
-  hipLaunchKernelGGL(reduce_rhs_kernel, g1, dim3(256), 0, s, a);
+template <int CC>
+static void trmv_pair(const SolveArgs& a, hipStream_t s) {
   const int pairs = (a.nj_max + 1) / 2;
   dim3 g2((pairs + 3) / 4, a.N * a.M);
-  hipLaunchKernelGGL(trmv_kernel<0>, g2, dim3(256), 0, s, a, (const double*)a.rhs, a.tmp);
-  hipLaunchKernelGGL(trmv_kernel<1>, g2, dim3(256), 0, s, a, (const double*)a.tmp, (double*)nullptr);
+  hipLaunchKernelGGL((trmv_kernel<0, CC>), g2, dim3(256), 0, s, a, (const double*)a.rhs, a.tmp);
+  hipLaunchKernelGGL((trmv_kernel<1, CC>), g2, dim3(256), 0, s, a, (const double*)a.tmp, (double*)nullptr);
+}
+
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
+  if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
+  dim3 g1((unsigned)(((int64_t)a.n * a.C + 255) / 256), a.N);
+  hipLaunchKernelGGL(reduce_rhs_kernel, g1, dim3(256), 0, s, a);
+  if (a.C == 1) trmv_pair<1>(a, s);
+  else if (a.C <= 4) trmv_pair<4>(a, s);
+  else if (a.C <= 10) trmv_pair<10>(a, s);
+  else trmv_pair<16>(a, s);
   return hipGetLastError();
 }
 

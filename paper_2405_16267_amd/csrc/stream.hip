@@ -25,13 +25,17 @@ namespace bca {
 
 // Per-sample omega-bar prox (Sec. 3.1, omega-bar step): with q = M w and
 // beta = rho_l / M minimise l(q; b) + (beta/2)(q - M c)^2 and return w = q / M.
-__device__ double prox_scalar(int loss, double c, double b, int M, double rho_l) {
+// w_prev (the previous omega-bar of the sample) only seeds the Newton iteration.
+__device__ double prox_scalar(int loss, double c, double b, int M, double rho_l, double w_prev) {
   if (loss == BCA_LOSS_SQUARED) return (2.0 * b + rho_l * c) / (2.0 * M + rho_l);
   // Logistic: root of -b sigmoid(-b q) + beta (q - Mc), bracketed in
-  // [Mc - 1/beta, Mc + 1/beta]; Newton steps kept inside the bracket by bisection.
+  // [Mc - 1/beta, Mc + 1/beta]; Newton steps kept inside the bracket by bisection,
+  // until the step is below a few ulp.
   const double beta = rho_l / M;
   const double q0 = M * c;
-  double lo = q0 - 1.0 / beta, hi = q0 + 1.0 / beta, q = q0;
+  double lo = q0 - 1.0 / beta, hi = q0 + 1.0 / beta;
+  double q = M * w_prev;
+  if (!(q > lo && q < hi)) q = q0;
   for (int it = 0; it < 100; ++it) {
     const double sg = 1.0 / (1.0 + exp(b * q));  // sigmoid(-b q)
     const double g = -b * sg + beta * (q - q0);
@@ -122,7 +126,8 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
         const int64_t gr = r0 + row;
         double nu = a.nu[gr];
         if (a.mode == 0) {
-          const double om = prox_scalar(a.loss, av + nu, a.b[gr], a.M, a.rho_l);
+          const double om = prox_scalar(a.loss, av + nu, a.b[gr], a.M, a.rho_l,
+                                        a.loss == BCA_LOSS_SQUARED ? 0.0 : a.omega[gr]);
           nu = nu + av - om;
           a.omega[gr] = om;
           a.nu[gr] = nu;
@@ -252,7 +257,7 @@ static hipError_t stream_dispatch(const StreamArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s) {
-  if (a.C != 1) return hipErrorInvalidValue;
+  if (a.C != 1) return launch_stream_mc(a, dtype, s);
   switch (dtype) {
     case BCA_F64: return stream_dispatch<double>(a, s);
     case BCA_F32: return stream_dispatch<float>(a, s);
@@ -335,7 +340,7 @@ static hipError_t objective_dispatch(const ObjArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_objective(const ObjArgs& a, int dtype, hipStream_t s) {
-  if (a.C != 1) return hipErrorInvalidValue;
+  if (a.C != 1) return launch_objective_mc(a, dtype, s);
   switch (dtype) {
     case BCA_F64: return objective_dispatch<double>(a, s);
     case BCA_F32: return objective_dispatch<float>(a, s);

@@ -36,7 +36,7 @@ def test_library_is_gfx950_code():
 def test_params_struct_layout_matches_header():
     import ctypes
     # loss..kappa (6 x int32), rows ptr, 4 doubles, 2 int32, 3 doubles, 2 int32 + uint32
-    assert ctypes.sizeof(bca.bca.Params) == 24 + 8 + 32 + 8 + 24 + 12 + 4
+    assert ctypes.sizeof(bca.Params) == 24 + 8 + 32 + 8 + 24 + 12 + 4
 
 
 def test_last_error_is_empty_string_initially():

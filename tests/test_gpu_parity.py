@@ -238,3 +238,59 @@ def test_error_paths():
     assert e.value.code == -1
     P.close()
     Q.close()
+
+
+# ------------------------------------------------------------------ softmax (C classes, row sparsity)
+def _softmax_gpu(w, dtype):
+    bca = _bca()
+    P = bca.Problem("softmax", w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
+                    rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=w.max_iters, dtype=dtype, n_classes=w.n_classes)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    return P
+
+
+def _softmax_oracle(w):
+    return oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
+                          w.gamma, w.rho_c, w.rho_b, w.rho_l, n_classes=w.n_classes)
+
+
+@pytest.mark.parametrize("dtype,C,tol", [("f64", 3, 1e-10), ("f32", 10, 1e-5)])
+def test_softmax_parity(dtype, C, tol):
+    bca = _bca()
+    w = datagen.softmax_workload(71, N=2, m_per=[300, 257], n=150, C=C, kappa=4, k_true=4,
+                                 n_blocks=2, dtype=dtype, max_iters=15)
+    P = _softmax_gpu(w, dtype)
+    o = _softmax_oracle(w)
+    P.step(1)
+    o.iterate(1, w.inner_iters)
+    for i in range(w.N):
+        assert rel(P.get_vector(bca.VEC_X, i).reshape(w.n, C), o.state.x[i]) < tol
+        assert rel(P.get_vector(bca.VEC_OMEGA, i).reshape(-1, C), o.state.omega[i]) < tol
+    assert rel(P.get_vector(bca.VEC_Z).reshape(w.n, C), o.state.z) < tol
+    P.step(w.max_iters - 1)
+    o.iterate(w.max_iters - 1, w.inner_iters)
+    assert o.topk_margin() > 10 * tol
+    assert np.array_equal(P.support(), o.support())
+    assert rel(P.coef(), o.coef()) < tol
+    f, fo = P.objective(), o.objective(o.coef())
+    assert abs(f - fo) <= tol * abs(fo)
+    h, ho = P.history(), np.array(o.state.history)
+    assert np.max(np.abs(h - ho) / np.maximum(np.abs(ho), 1e-2)) < 100 * tol
+    P.close()
+
+
+def test_softmax_rejects_bad_labels_and_shapes():
+    bca = _bca()
+    with pytest.raises(bca.BcaError) as e:
+        bca.Problem("softmax", 3000, [10], 1, 2, dtype="f32", n_classes=4)
+    assert e.value.code == -1
+    P = bca.Problem("softmax", 20, [30], 2, 2, dtype="f32", n_classes=4)
+    y = np.zeros(30, dtype=np.int32)
+    y[5] = 4
+    with pytest.raises(bca.BcaError) as e:
+        P.set_data(0, np.ones((30, 20), dtype=np.float32), y)
+    assert e.value.code == -1
+    P.close()

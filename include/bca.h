@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 typedef struct bca_problem_s* bca_problem;
+typedef struct bca_server_s* bca_server;
 
 /* Return codes. */
 enum {
@@ -186,6 +187,84 @@ int bca_destroy(bca_problem p);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* bca_last_error(void);
+
+/* ---------------------------------------------------------------- batched form
+ * Many independent problems (each created, loaded and finalized as above)
+ * advanced together in ONE persistent launch on hip_stream: every outer
+ * iteration of every problem is Algorithm 2's K_in inner iterations followed by
+ * the global step of Algorithm 1, exactly as bca_step computes it (to rounding:
+ * the batched streaming pass sums in a different order).  A problem's results do
+ * not depend on which other problems share the batch.  Limits: one-class losses
+ * (squared, logistic), FP32 or FP64 storage, n_j <= 1024, n <= 2048 (FP32) or
+ * 1024 (FP64).  The call synchronises hip_stream.
+ * Errors: BCA_E_INVALID (a problem outside the limits), BCA_E_STATE (not
+ * finalized), BCA_E_NONFINITE, BCA_E_DEVICE. */
+
+/* Advance every problem by min(outer_iters, its remaining max_iters) outer iterations. */
+int bca_batch_step(bca_problem* probs, int32_t count, int32_t outer_iters, void* hip_stream);
+
+/* Run every problem to its own max_iters. */
+int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream);
+
+/* Tile-shape autotuner of the batched streaming pass: groups the problems by
+ * (storage type, row length, rows per partition), times every candidate shape
+ * (rows per wavefront tile 1/2/4 x rows per work item 128/512/2048) on each group
+ * with a state-preserving streaming pass, and keeps the fastest per group.  The
+ * ADMM state is not modified. */
+int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream);
+
+/* Explicit tile shape of a problem in the batched form (rows per wavefront tile
+ * 1, 2 or 4; rows per work item >= 16) and its current value. */
+int bca_batch_set_shape(bca_problem p, int32_t rows_per_tile, int32_t rows_per_item);
+int bca_batch_get_shape(bca_problem p, int32_t* rows_per_tile, int32_t* rows_per_item);
+
+/* ---------------------------------------------------------------- serving form
+ * A request loop with continuous batching.  Each request is a complete sparse
+ * fit (the problem of Sec. 2 with its own data and parameters) run for its
+ * max_iters outer iterations.  A scheduler thread admits queued requests in
+ * arrival order while a slot is free and the request's device footprint fits
+ * hbm_budget_bytes, keeps their ADMM state resident, and advances all resident
+ * requests together in rounds of round_iters outer iterations (one-class
+ * requests in one batched persistent launch, softmax requests with their own
+ * kernels); finished requests are retired between rounds, freeing their slot and
+ * memory for waiting ones.  A request's result does not depend on the other
+ * requests it shares rounds with.  Submit/poll/fetch/cancel are thread-safe. */
+
+/* Request states reported by bca_server_poll. */
+enum { BCA_REQ_QUEUED = 0, BCA_REQ_RUNNING = 1, BCA_REQ_DONE = 2, BCA_REQ_FAILED = 3,
+       BCA_REQ_CANCELLED = 4 };
+
+/* Start a server (its scheduler thread) on hip_stream.
+ * Errors: BCA_E_INVALID (max_slots < 1, round_iters < 1, zero budget). */
+int bca_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t round_iters, void* hip_stream,
+                      bca_server* out);
+
+/* Queue a request: params as for bca_create (params->rows read here), A[i] and
+ * b[i] host pointers of partition i laid out as for bca_set_data with ld = n;
+ * both are copied before the call returns.  *ticket identifies the request.
+ * Errors: BCA_E_INVALID, BCA_E_BUDGET (the request alone exceeds the budget). */
+int bca_server_submit(bca_server s, const bca_params* params, const void* const* A, const void* const* b,
+                      uint64_t* ticket);
+
+/* Current BCA_REQ_* state of a request.  Errors: BCA_E_NOTFOUND. */
+int bca_server_poll(bca_server s, uint64_t ticket, int32_t* state);
+
+/* Results of a finished request (host memory, any pointer may be NULL): the
+ * support (kappa int32, ascending), x_hat (n*C doubles), the objective and the
+ * latency from submit to retirement in seconds.
+ * Errors: BCA_E_NOTFOUND, BCA_E_STATE (not finished), BCA_E_CANCELLED,
+ * BCA_E_DEVICE (the request failed). */
+int bca_server_fetch(bca_server s, uint64_t ticket, int32_t* idx, double* x, double* f, double* lat_s);
+
+/* Cancel a queued or running request; its slot and memory are released at the
+ * next round boundary.  Errors: BCA_E_NOTFOUND. */
+int bca_server_cancel(bca_server s, uint64_t ticket);
+
+/* Queue length, resident requests, reserved device bytes and rounds run so far. */
+int bca_server_stats(bca_server s, int32_t* queued, int32_t* running, double* used_bytes, int64_t* rounds);
+
+/* Stop the scheduler and release every resident request. */
+int bca_server_destroy(bca_server s);
 
 /* The top-kappa projection of the s-step (Sec. 3), as a standalone device
  * primitive: idx (device, kappa int32) receives the indices of the kappa

@@ -28,7 +28,10 @@ EXPORTS = ["bca_create", "bca_set_data", "bca_finalize", "bca_step", "bca_solve"
            "bca_get_support", "bca_get_coef", "bca_get_residuals", "bca_get_history",
            "bca_get_objective", "bca_get_vector", "bca_set_vector", "bca_get_state",
            "bca_set_state", "bca_get_factor", "bca_set_timing", "bca_get_timing", "bca_destroy",
-           "bca_last_error", "bca_topk"]
+           "bca_last_error", "bca_topk", "bca_batch_step", "bca_batch_solve",
+           "bca_batch_autotune", "bca_batch_set_shape", "bca_batch_get_shape",
+           "bca_server_create", "bca_server_submit", "bca_server_poll", "bca_server_fetch",
+           "bca_server_cancel", "bca_server_stats", "bca_server_destroy"]
 
 
 class BcaError(RuntimeError):
@@ -77,6 +80,18 @@ def _load():
         "bca_get_timing": [P, i32, pi32, pdbl],
         "bca_destroy": [P],
         "bca_topk": [P, i32, i64, i32, P, P],
+        "bca_batch_step": [P, i32, i32, P],
+        "bca_batch_solve": [P, i32, P],
+        "bca_batch_autotune": [P, i32, P],
+        "bca_batch_set_shape": [P, i32, i32],
+        "bca_batch_get_shape": [P, pi32, pi32],
+        "bca_server_create": [ctypes.c_size_t, i32, i32, P, ctypes.POINTER(P)],
+        "bca_server_submit": [P, ctypes.POINTER(Params), P, P, ctypes.POINTER(ctypes.c_uint64)],
+        "bca_server_poll": [P, ctypes.c_uint64, pi32],
+        "bca_server_fetch": [P, ctypes.c_uint64, P, P, pdbl, pdbl],
+        "bca_server_cancel": [P, ctypes.c_uint64],
+        "bca_server_stats": [P, pi32, pi32, pdbl, ctypes.POINTER(ctypes.c_int64)],
+        "bca_server_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -260,6 +275,14 @@ class Problem:
         _check(_lib.bca_get_factor(self._h, part, block, _ptr(W)))
         return W
 
+    def batch_shape(self):
+        t, i = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.bca_batch_get_shape(self._h, ctypes.byref(t), ctypes.byref(i)))
+        return t.value, i.value
+
+    def set_batch_shape(self, rows_per_tile: int, rows_per_item: int):
+        _check(_lib.bca_batch_set_shape(self._h, rows_per_tile, rows_per_item))
+
     def set_timing(self, on: bool = True):
         _check(_lib.bca_set_timing(self._h, 1 if on else 0))
 
@@ -279,3 +302,93 @@ def topk(z, kappa: int):
     _check(_lib.bca_topk(ctypes.c_void_p(z.data_ptr()), dt, z.numel(), kappa,
                          ctypes.c_void_p(idx.data_ptr()), _current_stream()))
     return idx
+
+
+def _handles(problems):
+    arr = (ctypes.c_void_p * len(problems))(*[p._h.value for p in problems])
+    return arr
+
+
+def batch_step(problems, outer_iters: int, stream=None):
+    """Advance every problem by up to outer_iters outer iterations in one persistent launch."""
+    st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+    _check(_lib.bca_batch_step(_handles(problems), len(problems), outer_iters, st))
+
+
+def batch_solve(problems, stream=None):
+    st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+    _check(_lib.bca_batch_solve(_handles(problems), len(problems), st))
+
+
+def batch_autotune(problems, stream=None):
+    st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+    _check(_lib.bca_batch_autotune(_handles(problems), len(problems), st))
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = range(5)
+
+
+class Server:
+    """Continuous-batching request loop (bca_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, round_iters: int = 5,
+                 stream=None):
+        st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(_lib.bca_server_create(hbm_budget_bytes, max_slots, round_iters, st, ctypes.byref(h)))
+        self._h = h
+        self._meta = {}
+
+    def submit(self, loss: str, A_parts, b_parts, n_blocks: int, kappa: int, gamma=10.0,
+               rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5, max_iters=100, dtype="f32",
+               n_classes=1) -> int:
+        N = len(A_parts)
+        rows = (ctypes.c_int64 * N)(*[a.shape[0] for a in A_parts])
+        n = A_parts[0].shape[1]
+        p = Params(loss=LOSS[loss], n_features=n, n_classes=n_classes, n_partitions=N,
+                   n_blocks=n_blocks, kappa=kappa, rows=rows, gamma=gamma, rho_c=rho_c,
+                   rho_b=rho_b, rho_l=rho_l, inner_iters=inner_iters, max_iters=max_iters,
+                   tol_p=0.0, tol_d=0.0, tol_b=0.0, a_dtype=DTYPE[dtype], check_every=0, flags=0)
+        As = [np.ascontiguousarray(a, dtype=_NP_DTYPE[dtype]) for a in A_parts]
+        bs = [np.ascontiguousarray(b, dtype=np.int32 if loss == "softmax" else np.float64)
+              for b in b_parts]
+        pa = (ctypes.c_void_p * N)(*[a.ctypes.data for a in As])
+        pb = (ctypes.c_void_p * N)(*[b.ctypes.data for b in bs])
+        t = ctypes.c_uint64()
+        _check(_lib.bca_server_submit(self._h, ctypes.byref(p), pa, pb, ctypes.byref(t)))
+        self._meta[t.value] = (n, kappa, n_classes)
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        s = ctypes.c_int32()
+        _check(_lib.bca_server_poll(self._h, ticket, ctypes.byref(s)))
+        return s.value
+
+    def fetch(self, ticket: int):
+        n, kappa, C = self._meta[ticket]
+        idx = np.zeros(kappa, dtype=np.int32)
+        x = np.zeros(n * C)
+        f, lat = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.bca_server_fetch(self._h, ticket, _ptr(idx), _ptr(x), ctypes.byref(f),
+                                     ctypes.byref(lat)))
+        return idx, (x if C == 1 else x.reshape(n, C)), f.value, lat.value
+
+    def cancel(self, ticket: int):
+        _check(_lib.bca_server_cancel(self._h, ticket))
+
+    def stats(self):
+        q, r, u, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.bca_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(u),
+                                     ctypes.byref(k)))
+        return dict(queued=q.value, running=r.value, used_bytes=u.value, rounds=k.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.bca_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

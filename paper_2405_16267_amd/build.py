@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbca.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["bca_api.hip", "stream.hip", "stream_mc.hip", "setup.hip", "solve.hip", "global.hip"]
+SOURCES = ["bca_api.hip", "stream.hip", "stream_mc.hip", "setup.hip", "solve.hip", "global.hip",
+           "batch.hip", "server.hip"]
 ARCH = os.environ.get("BCA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -29,7 +30,8 @@ FLAGS = [
 
 def _inputs():
     deps = [os.path.join(CSRC, s) for s in SOURCES]
-    deps += [os.path.join(CSRC, "bca_internal.h"), os.path.join(INCLUDE, "bca.h")]
+    deps += [os.path.join(CSRC, h) for h in ("bca_internal.h", "global_impl.h", "prox_impl.h")]
+    deps += [os.path.join(INCLUDE, "bca.h")]
     return deps
 
 

@@ -17,6 +17,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -89,6 +91,11 @@ struct bca_problem_s {
   bool need_prime = false;
   int iter = 0;
   bool timing = false;
+  // batched form: wave partial sums of A^T e, tile shape, staleness
+  double* bgpart = nullptr;
+  size_t bgpart_count = 0;
+  int b_rows_tile = 0, b_rows_item = 0;   // 0 = default shape
+  bool need_bprime = true;
   std::vector<TimedPair> pending[5];
   int launches[5] = {0, 0, 0, 0, 0};
   double total_ms[5] = {0, 0, 0, 0, 0};
@@ -539,6 +546,7 @@ int bca_finalize(bca_problem P) {
   if (st) return fail(BCA_E_NONFINITE, "finalize: a block matrix K_ij is not positive definite");
   P->finalized = true;
   P->need_prime = false;
+  P->need_bprime = true;
   P->iter = 0;
   return BCA_OK;
 }
@@ -549,6 +557,7 @@ int bca_step(bca_problem P, int32_t outer_iters, int32_t* iters_done) {
   if (outer_iters < 0) return fail(BCA_E_INVALID, "negative iteration count");
   if (P->need_prime) TRY(prime(P));
   for (int k = 0; k < outer_iters; ++k) TRY(one_outer(P));
+  if (outer_iters > 0) P->need_bprime = true;
   if (iters_done) *iters_done = P->iter;
   return BCA_OK;
 }
@@ -562,6 +571,7 @@ int bca_solve(bca_problem P, int32_t* iters_done, int32_t* converged) {
   while (P->iter < P->p.max_iters) {
     const int k = std::min(every, P->p.max_iters - P->iter);
     for (int q = 0; q < k; ++q) TRY(one_outer(P));
+    P->need_bprime = true;
     double sc[6];
     HIP_TRY(hipMemcpyAsync(sc, P->scal, sizeof(sc), hipMemcpyDeviceToHost, P->stream));
     TRY(check_status(P, "solve"));
@@ -715,6 +725,7 @@ int bca_set_vector(bca_problem P, int32_t which, int32_t part, const double* in)
   HIP_TRY(hipMemcpyAsync(dst, in, cnt * sizeof(double), hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->need_prime = true;
+  P->need_bprime = true;
   return BCA_OK;
 }
 
@@ -786,6 +797,7 @@ int bca_set_state(bca_problem P, const void* buf, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(P->stream));
   P->iter = h.iter;
   P->need_prime = true;
+  P->need_bprime = true;
   return BCA_OK;
 }
 
@@ -840,6 +852,325 @@ int bca_topk(const void* z, int32_t dtype, int64_t n, int32_t kappa, int32_t* id
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   TRY(launch_ok(launch_topk(z, dtype == BCA_F64, n, kappa, idx, nullptr, s), "topk"));
   HIP_TRY(hipStreamSynchronize(s));
+  return BCA_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================= batched form
+namespace {
+
+std::mutex g_batch_mu;
+struct BatchContext {
+  void* buf = nullptr;   // descriptors + item lists + counters
+  size_t cap = 0;
+};
+BatchContext g_batch;
+
+int batch_rows_tile(bca_problem P) { return P->b_rows_tile > 0 ? P->b_rows_tile : 2; }
+int batch_rows_item(bca_problem P) { return P->b_rows_item > 0 ? P->b_rows_item : 512; }
+
+int batch_check(bca_problem P) {
+  if (!P) return fail(BCA_E_INVALID, "null problem in batch");
+  if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
+  if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
+  if (P->dtype == BCA_BF16) return fail(BCA_E_INVALID, "the batched form streams FP32 or FP64 data");
+  if (P->nj_max > 1024 || P->nvec > batch_max_nvec())
+    return fail(BCA_E_INVALID, "batched problems need n_j <= 1024 and n <= 64*8 vectors per row");
+  if (batch_shape_code(P->nvec, batch_rows_tile(P)) < 0)
+    return fail(BCA_E_INVALID, "no batched tile shape with %d rows per tile for n = %d", batch_rows_tile(P), P->n);
+  return BCA_OK;
+}
+
+int batch_check_basic(bca_problem P) {
+  if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
+  if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
+  if (P->dtype == BCA_BF16) return fail(BCA_E_INVALID, "the batched form streams FP32 or FP64 data");
+  if (P->nj_max > 1024 || P->nvec > batch_max_nvec())
+    return fail(BCA_E_INVALID, "batched problems need n_j <= 1024 and n <= 64*8 vectors per row");
+  return BCA_OK;
+}
+
+int64_t batch_items_per_part(bca_problem P) {
+  int64_t mx = 0;
+  for (auto r : P->rows) mx = std::max(mx, r);
+  return (mx + batch_rows_item(P) - 1) / batch_rows_item(P);
+}
+
+int batch_ensure_partials(bca_problem P) {
+  const size_t need = (size_t)P->N * batch_items_per_part(P) * 4 * P->ld;
+  if (P->bgpart && P->bgpart_count >= need) return BCA_OK;
+  if (P->bgpart) dfree(P, P->bgpart);
+  P->bgpart = nullptr;
+  TRY(dalloc(P, &P->bgpart, need));
+  P->bgpart_count = need;
+  P->need_bprime = true;
+  return BCA_OK;
+}
+
+BatchInst batch_desc(bca_problem P, int outer) {
+  BatchInst I{};
+  I.A = P->A;
+  I.ld = P->ld;
+  I.row_off = P->d_row_off;
+  I.b = P->b;
+  I.omega = P->omega;
+  I.nu = P->nu;
+  I.xs = P->xs;
+  I.x = P->x;
+  I.u = P->u;
+  I.z = P->z;
+  I.s = P->s;
+  I.scal = P->scal;
+  I.hist = P->hist;
+  I.support = P->support;
+  I.work = P->work;
+  I.status = P->status;
+  I.gpart = P->bgpart;
+  I.wr = P->wr;
+  I.wc = P->wc;
+  I.fac_off = P->d_fac_off;
+  I.col_off = P->d_col_off;
+  I.N = P->N;
+  I.M = P->M;
+  I.n = P->n;
+  I.kappa = P->kappa;
+  I.loss = P->p.loss;
+  I.dtype = P->dtype;
+  I.nvec = P->nvec;
+  I.hist_cap = P->p.max_iters;
+  I.inner_iters = P->p.inner_iters;
+  I.rows_per_item = batch_rows_item(P);
+  I.items_per_part = (int)batch_items_per_part(P);
+  I.shape = batch_shape_code(P->nvec, batch_rows_tile(P));
+  I.outer = outer;
+  I.rho_l = P->p.rho_l;
+  I.rho_c = P->p.rho_c;
+  I.rho_b = P->p.rho_b;
+  I.shift = P->shift;
+  I.inv_M = 1.0 / P->M;
+  return I;
+}
+
+// One persistent launch: optional prime phase for problems whose partial sums
+// are stale, then `outer[i]` outer iterations of problem i.  stream_only runs
+// just the prime phase over all given problems (tile-shape timing).
+int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, hipStream_t s,
+                 bool stream_only, float* ms) {
+  std::vector<BatchInst> desc(count);
+  std::vector<BatchItem> solve, stream, primei;
+  int outer_max = 0, inner_max = 0;
+  for (int r = 0; r < count; ++r) {
+    bca_problem P = probs[r];
+    TRY(batch_ensure_partials(P));
+    desc[r] = batch_desc(P, outer[r]);
+    outer_max = std::max(outer_max, outer[r]);
+    inner_max = std::max(inner_max, P->p.inner_iters);
+    const int ipp = desc[r].items_per_part;
+    for (int i = 0; i < P->N; ++i) {
+      for (int j = 0; j < P->M; ++j) solve.push_back({r, i, j, 0});
+      for (int c = 0; c < ipp; ++c) {
+        stream.push_back({r, i, c, 0});
+        if (P->need_bprime || stream_only) primei.push_back({r, i, c, 0});
+      }
+    }
+  }
+  // largest work first: solve items by n_j^2, stream items by rows x vectors
+  auto solve_cost = [&](const BatchItem& w) {
+    bca_problem P = probs[w.inst];
+    const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
+    return nj * nj;
+  };
+  auto stream_cost = [&](const BatchItem& w) {
+    bca_problem P = probs[w.inst];
+    const int64_t lo = (int64_t)w.b * batch_rows_item(P);
+    const int64_t rows = std::max<int64_t>(0, std::min<int64_t>(P->rows[w.a], lo + batch_rows_item(P)) - lo);
+    return rows * P->nvec;
+  };
+  std::stable_sort(solve.begin(), solve.end(), [&](const BatchItem& a, const BatchItem& b) {
+    return solve_cost(a) > solve_cost(b);
+  });
+  std::stable_sort(stream.begin(), stream.end(), [&](const BatchItem& a, const BatchItem& b) {
+    return stream_cost(a) > stream_cost(b);
+  });
+  std::stable_sort(primei.begin(), primei.end(), [&](const BatchItem& a, const BatchItem& b) {
+    return stream_cost(a) > stream_cost(b);
+  });
+  if (stream_only) outer_max = 0;
+  const int phases = (primei.empty() ? 0 : 1) + outer_max * (2 * inner_max + 1);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t off_desc = 0;
+  const size_t off_solve = off_desc + al(desc.size() * sizeof(BatchInst));
+  const size_t off_stream = off_solve + al(solve.size() * sizeof(BatchItem));
+  const size_t off_prime = off_stream + al(stream.size() * sizeof(BatchItem));
+  const size_t off_cnt = off_prime + al(primei.size() * sizeof(BatchItem));
+  const size_t total = off_cnt + al((size_t)std::max(phases, 1) * sizeof(unsigned int));
+  if (g_batch.cap < total) {
+    if (g_batch.buf) (void)hipFree(g_batch.buf);
+    g_batch.buf = nullptr;
+    g_batch.cap = 0;
+    HIP_TRY(hipMalloc(&g_batch.buf, total));
+    g_batch.cap = total;
+  }
+  char* base = reinterpret_cast<char*>(g_batch.buf);
+  HIP_TRY(hipMemcpyAsync(base + off_desc, desc.data(), desc.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s));
+  if (!solve.empty())
+    HIP_TRY(hipMemcpyAsync(base + off_solve, solve.data(), solve.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  if (!stream.empty())
+    HIP_TRY(hipMemcpyAsync(base + off_stream, stream.data(), stream.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  if (!primei.empty())
+    HIP_TRY(hipMemcpyAsync(base + off_prime, primei.data(), primei.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(base + off_cnt, 0, (size_t)std::max(phases, 1) * sizeof(unsigned int), s));
+  BatchArgs a{};
+  a.inst = reinterpret_cast<const BatchInst*>(base + off_desc);
+  a.count = count;
+  a.solve_items = reinterpret_cast<const BatchItem*>(base + off_solve);
+  a.n_solve = (int)solve.size();
+  a.stream_items = reinterpret_cast<const BatchItem*>(base + off_stream);
+  a.n_stream = (int)stream.size();
+  a.prime_items = reinterpret_cast<const BatchItem*>(base + off_prime);
+  a.n_prime = (int)primei.size();
+  a.outer = outer_max;
+  a.inner_max = inner_max;
+  a.counters = reinterpret_cast<unsigned int*>(base + off_cnt);
+  a.stream_only = stream_only ? 1 : 0;
+  const int grid = batch_grid_size();
+  if (grid < 1) return fail(BCA_E_DEVICE, "batched kernel does not fit on this device");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+  }
+  hipError_t le = launch_batch(a, grid, s);
+  if (le != hipSuccess) return fail(BCA_E_DEVICE, "batched launch failed: %s", hipGetErrorString(le));
+  if (ms) HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ms) {
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  for (int r = 0; r < count; ++r) {
+    bca_problem P = probs[r];
+    if (stream_only) {
+      P->need_bprime = true;
+      continue;
+    }
+    P->need_bprime = false;
+    if (outer[r] > 0) {
+      P->iter += outer[r];
+      P->need_prime = true;
+    }
+  }
+  return BCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bca_batch_step(bca_problem* probs, int32_t count, int32_t outer_iters, void* hip_stream) {
+  if (!probs || count < 1) return fail(BCA_E_INVALID, "empty batch");
+  if (outer_iters < 0) return fail(BCA_E_INVALID, "negative iteration count");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  std::vector<int> outer(count);
+  for (int r = 0; r < count; ++r) {
+    TRY(batch_check(probs[r]));
+    outer[r] = std::max(0, std::min(outer_iters, probs[r]->p.max_iters - probs[r]->iter));
+  }
+  TRY(batch_launch(probs, count, outer, reinterpret_cast<hipStream_t>(hip_stream), false, nullptr));
+  for (int r = 0; r < count; ++r) TRY(check_status(probs[r], "batch"));
+  return BCA_OK;
+}
+
+int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream) {
+  if (!probs || count < 1) return fail(BCA_E_INVALID, "empty batch");
+  int32_t most = 0;
+  for (int r = 0; r < count; ++r) {
+    if (!probs[r]) return fail(BCA_E_INVALID, "null problem in batch");
+    most = std::max(most, probs[r]->p.max_iters - probs[r]->iter);
+  }
+  return bca_batch_step(probs, count, most, hip_stream);
+}
+
+int bca_batch_set_shape(bca_problem P, int32_t rows_per_tile, int32_t rows_per_item) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (rows_per_tile != 1 && rows_per_tile != 2 && rows_per_tile != 4)
+    return fail(BCA_E_INVALID, "rows_per_tile must be 1, 2 or 4");
+  if (rows_per_item < 16 || rows_per_item > (1 << 20)) return fail(BCA_E_INVALID, "rows_per_item out of range");
+  if (batch_shape_code(P->nvec, rows_per_tile) < 0)
+    return fail(BCA_E_INVALID, "no batched tile shape with %d rows per tile for n = %d", rows_per_tile, P->n);
+  P->b_rows_tile = rows_per_tile;
+  P->b_rows_item = rows_per_item;
+  P->need_bprime = true;
+  return BCA_OK;
+}
+
+int bca_batch_get_shape(bca_problem P, int32_t* rows_per_tile, int32_t* rows_per_item) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  if (rows_per_tile) *rows_per_tile = batch_rows_tile(P);
+  if (rows_per_item) *rows_per_item = batch_rows_item(P);
+  return BCA_OK;
+}
+
+int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
+  if (!probs || count < 1) return fail(BCA_E_INVALID, "empty batch");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  // buckets: (storage type, chunks per lane, log2 of the largest partition)
+  std::vector<std::vector<bca_problem>> buckets;
+  std::vector<std::tuple<int, int, int>> keys;
+  for (int r = 0; r < count; ++r) {
+    bca_problem P = probs[r];
+    if (!P || !P->finalized) return fail(BCA_E_STATE, "autotune needs finalized problems");
+    int nc = 1;
+    while (nc < 8 && 64 * nc < P->nvec) nc *= 2;
+    int64_t mx = 0;
+    for (auto v : P->rows) mx = std::max(mx, v);
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= mx) ++lg;
+    auto key = std::make_tuple(P->dtype, nc, lg);
+    size_t b = 0;
+    for (; b < keys.size(); ++b)
+      if (keys[b] == key) break;
+    if (b == keys.size()) {
+      keys.push_back(key);
+      buckets.emplace_back();
+    }
+    buckets[b].push_back(P);
+  }
+  const int tiles[3] = {1, 2, 4};
+  const int items[3] = {128, 512, 2048};
+  for (size_t b = 0; b < buckets.size(); ++b) {
+    auto& bp = buckets[b];
+    for (auto P : bp) TRY(batch_check_basic(P));
+    float best = 1e30f;
+    int bt = 2, bi = 512;
+    for (int ti = 0; ti < 3; ++ti) {
+      if (batch_shape_code(bp[0]->nvec, tiles[ti]) < 0) continue;
+      for (int ii = 0; ii < 3; ++ii) {
+        for (auto P : bp) {
+          P->b_rows_tile = tiles[ti];
+          P->b_rows_item = items[ii];
+        }
+        std::vector<int> outer(bp.size(), 0);
+        float ms = 0.f, ms2 = 0.f;
+        TRY(batch_launch(bp.data(), (int)bp.size(), outer, s, true, &ms));   // warm
+        TRY(batch_launch(bp.data(), (int)bp.size(), outer, s, true, &ms2));
+        if (ms2 < best) {
+          best = ms2;
+          bt = tiles[ti];
+          bi = items[ii];
+        }
+      }
+    }
+    for (auto P : bp) {
+      P->b_rows_tile = bt;
+      P->b_rows_item = bi;
+      P->need_bprime = true;
+    }
+  }
   return BCA_OK;
 }
 

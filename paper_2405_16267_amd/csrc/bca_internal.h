@@ -183,6 +183,59 @@ hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* id
 hipError_t launch_support(const double* z, int n, int C, int kappa, int32_t* idx, double* work,
                           hipStream_t s);
 
+// ------------------------------------------------------------------ batched form
+// Device-side descriptor of one problem of a batch (all pointers are that
+// problem's own device buffers).
+struct BatchInst {
+  const void* A;
+  int64_t ld;
+  const int64_t* row_off;
+  const double* b;
+  double* omega;
+  double* nu;
+  void* xs;                // N x ld streaming copy of x (FP32 or FP64)
+  double* x;
+  double* u;
+  double* z;
+  double* s;
+  double* scal;
+  double* hist;
+  int32_t* support;
+  double* work;
+  int* status;
+  double* gpart;           // N x (items_per_part * 4) x ld wave partials of A^T e
+  const double* wr;
+  const double* wc;
+  const int64_t* fac_off;
+  const int32_t* col_off;
+  int N, M, n, kappa, loss, dtype, nvec, hist_cap, inner_iters;
+  int rows_per_item, items_per_part, shape;   // stream tile shape (see batch.hip)
+  int outer;               // outer iterations this launch runs for the problem
+  double rho_l, rho_c, rho_b, shift, inv_M;
+};
+
+struct BatchItem {
+  int inst, a, b, c;
+};
+
+struct BatchArgs {
+  const BatchInst* inst;
+  int count;
+  const BatchItem* solve_items;    // (inst, partition, block), largest first
+  int n_solve;
+  const BatchItem* stream_items;   // (inst, partition, chunk), largest first
+  int n_stream;
+  const BatchItem* prime_items;    // stream items of problems whose partial sums are stale
+  int n_prime;
+  int outer, inner_max;
+  unsigned int* counters;          // one work counter per phase, zeroed before the launch
+  int stream_only;                 // 1: run only the prime phase (tile-shape timing)
+};
+hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
+int batch_grid_size();            // co-resident workgroups of the batched kernel
+int batch_shape_code(int nvec, int R);  // -1 if the (chunks per lane, rows per tile) pair is not built
+int batch_max_nvec();
+
 // Non-finite scan of a device buffer of `count` elements (dtype BCA_*), plus an
 // optional label range check; sets *flag nonzero if anything is off.
 hipError_t launch_check(const void* p, int dtype, int64_t count, int* flag, hipStream_t s);

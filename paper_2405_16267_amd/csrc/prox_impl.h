@@ -1,0 +1,37 @@
+// Per-sample omega-bar prox of the node-level loop (Sec. 3.1), shared by the
+// one-problem and the batched streaming passes.
+#pragma once
+#include "bca_internal.h"
+
+namespace bca {
+
+// Per-sample omega-bar prox (Sec. 3.1, omega-bar step): with q = M w and
+// beta = rho_l / M minimise l(q; b) + (beta/2)(q - M c)^2 and return w = q / M.
+// w_prev (the previous omega-bar of the sample) only seeds the Newton iteration.
+__device__ __forceinline__ double prox_scalar(int loss, double c, double b, int M, double rho_l, double w_prev) {
+  if (loss == BCA_LOSS_SQUARED) return (2.0 * b + rho_l * c) / (2.0 * M + rho_l);
+  // Logistic: root of -b sigmoid(-b q) + beta (q - Mc), bracketed in
+  // [Mc - 1/beta, Mc + 1/beta]; Newton steps kept inside the bracket by bisection,
+  // until the step is below a few ulp.
+  const double beta = rho_l / M;
+  const double q0 = M * c;
+  double lo = q0 - 1.0 / beta, hi = q0 + 1.0 / beta;
+  double q = M * w_prev;
+  if (!(q > lo && q < hi)) q = q0;
+  for (int it = 0; it < 100; ++it) {
+    const double sg = 1.0 / (1.0 + exp(b * q));  // sigmoid(-b q)
+    const double g = -b * sg + beta * (q - q0);
+    if (g == 0.0) break;
+    if (g < 0.0) lo = q; else hi = q;
+    const double h = sg * (1.0 - sg) + beta;
+    double qn = q - g / h;
+    if (!(qn > lo && qn < hi)) qn = 0.5 * (lo + hi);
+    const double tol = 4.0 * 2.220446049250313e-16 * fabs(q);
+    const bool done = fabs(qn - q) <= tol || (hi - lo) <= tol;
+    q = qn;
+    if (done) break;
+  }
+  return q / M;
+}
+
+}  // namespace bca

@@ -1,0 +1,149 @@
+"""Batched form: many uneven problems in one persistent launch.
+
+Checks: each problem of a batch matches its solo run of the one-problem path
+(FP64 1e-12, FP32 1e-5) and the FP64 oracle; a problem gives the same bits alone
+and inside a mix; the tile-shape autotuner leaves the ADMM state untouched.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+LOSS_NAME = {0: "squared", 1: "logistic"}
+
+
+def _bca():
+    import paper_2405_16267_amd as bca
+    return bca
+
+
+def make(w):
+    bca = _bca()
+    P = bca.Problem(LOSS_NAME[w.loss], w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma,
+                    rho_c=w.rho_c, rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=w.max_iters, dtype=w.dtype)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    return P
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def mix(dtype="f32", K=12):
+    specs = [(0, 700, 53), (1, 1300, 130), (2, 4100, 517), (3, 950, 1100), (4, 2600, 260),
+             (5, 520, 77)]
+    out = []
+    for r, m, n in specs:
+        w = datagen.batched_instance(r, m, n, dtype=dtype, max_iters=K)
+        out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_batch_matches_solo_runs(dtype, tol):
+    bca = _bca()
+    ws = mix(dtype)
+    if dtype == "f64":
+        ws = [w for w in ws if w.n <= 1024]
+    batch = [make(w) for w in ws]
+    solo = [make(w) for w in ws]
+    bca.batch_step(batch, 12)
+    for w, B, S in zip(ws, batch, solo):
+        S.step(12)
+        assert B.residuals()[3] == 12
+        hb, hs = B.history(), S.history()
+        assert hb.shape == hs.shape == (12, 3)
+        assert np.max(np.abs(hb - hs) / np.maximum(np.abs(hs), 1e-2)) < 100 * tol, w.name
+        assert rel(B.get_vector(bca.VEC_Z), S.get_vector(bca.VEC_Z)) < tol, w.name
+        assert np.array_equal(B.support(), S.support()), w.name
+    for P in batch + solo:
+        P.close()
+
+
+def test_batch_problem_alone_equals_in_mix():
+    bca = _bca()
+    ws = mix("f32", K=8)
+    alone = make(ws[2])
+    together = [make(w) for w in ws]
+    bca.batch_step([alone], 8)
+    bca.batch_step(together, 8)
+    assert np.array_equal(alone.get_vector(bca.VEC_Z), together[2].get_vector(bca.VEC_Z))
+    assert np.array_equal(alone.history(), together[2].history())
+    for i in range(ws[2].N):
+        assert np.array_equal(alone.get_vector(bca.VEC_NU, i), together[2].get_vector(bca.VEC_NU, i))
+    for P in [alone] + together:
+        P.close()
+
+
+def test_batch_against_oracle_f64():
+    bca = _bca()
+    w = datagen.batched_instance(6, 1200, 90, dtype="f64", max_iters=20)
+    P = make(w)
+    bca.batch_step([P], 7)
+    bca.batch_step([P], 13)          # two launches: the state carries over
+    o = oracle.BiCADMM(w.A, w.b, w.loss, w.n_blocks, w.kappa, w.gamma, w.rho_c, w.rho_b, w.rho_l)
+    o.iterate(20, w.inner_iters)
+    assert rel(P.get_vector(bca.VEC_Z), o.state.z) < 1e-12
+    assert np.array_equal(P.support(), o.support())
+    h, ho = P.history(), np.array(o.state.history)
+    assert np.max(np.abs(h - ho) / np.maximum(np.abs(ho), 1e-3)) < 1e-9
+    P.close()
+
+
+def test_batch_respects_each_max_iters_and_mixes_with_plain_steps():
+    bca = _bca()
+    a = datagen.batched_instance(8, 800, 64, dtype="f64", max_iters=5)
+    b = datagen.batched_instance(9, 900, 70, dtype="f64", max_iters=9)
+    A, B = make(a), make(b)
+    bca.batch_solve([A, B])
+    assert A.residuals()[3] == 5 and B.residuals()[3] == 9
+    # plain and batched steps interleave on one problem
+    C = make(b)
+    C.step(4)
+    bca.batch_step([C], 3)
+    C.step(2)
+    assert C.residuals()[3] == 9
+    assert rel(C.get_vector(bca.VEC_Z), B.get_vector(bca.VEC_Z)) < 1e-12
+    for P in (A, B, C):
+        P.close()
+
+
+def test_batch_autotune_keeps_state_and_results():
+    bca = _bca()
+    ws = mix("f32", K=6)
+    P = [make(w) for w in ws]
+    Q = [make(w) for w in ws]
+    bca.batch_step(P, 3)
+    bca.batch_step(Q, 3)
+    z_before = [p.get_vector(bca.VEC_Z) for p in P]
+    bca.batch_autotune(P)
+    for p, zb in zip(P, z_before):
+        assert np.array_equal(p.get_vector(bca.VEC_Z), zb)
+        t, i = p.batch_shape()
+        assert t in (1, 2, 4) and i in (128, 512, 2048)
+    bca.batch_step(P, 3)
+    bca.batch_step(Q, 3)
+    for p, q in zip(P, Q):
+        assert rel(p.get_vector(bca.VEC_Z), q.get_vector(bca.VEC_Z)) < 1e-5
+    for x in P + Q:
+        x.close()
+
+
+def test_batch_rejects_out_of_scope_problems():
+    bca = _bca()
+    w = datagen.softmax_workload(3, N=2, m_per=40, n=20, C=3, kappa=2, k_true=2, n_blocks=2)
+    S = bca.Problem("softmax", w.n, w.rows, 2, 2, dtype="f32", n_classes=3)
+    for i in range(2):
+        S.set_data(i, w.A[i], w.b[i])
+    S.finalize()
+    with pytest.raises(bca.BcaError) as e:
+        bca.batch_step([S], 1)
+    assert e.value.code == -1
+    S.close()

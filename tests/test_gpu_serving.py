@@ -1,0 +1,116 @@
+"""Serving form: continuous batching of sparse-fit requests.
+
+Checks: every served result matches the same request solved alone with the
+one-problem path (FP64 1e-12, FP32 1e-5); a request's result is bitwise the same
+alone on a server and in a mix; admission by HBM budget, slot limit and
+cancellation behave as documented.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+LOSS_NAME = {0: "squared", 1: "logistic", 2: "softmax"}
+
+
+def _bca():
+    import paper_2405_16267_amd as bca
+    return bca
+
+
+def submit(S, w):
+    return S.submit(LOSS_NAME[w.loss], w.A, w.b, w.n_blocks, w.kappa, gamma=w.gamma,
+                    rho_c=w.rho_c, rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=w.max_iters, dtype=w.dtype, n_classes=w.n_classes)
+
+
+def wait_all(S, tickets, timeout=120.0):
+    bca = _bca()
+    t0 = time.time()
+    while True:
+        st = [S.poll(t) for t in tickets]
+        if all(s in (bca.REQ_DONE, bca.REQ_FAILED, bca.REQ_CANCELLED) for s in st):
+            return st
+        assert time.time() - t0 < timeout, st
+        time.sleep(0.01)
+
+
+def solo(w):
+    bca = _bca()
+    P = bca.Problem(LOSS_NAME[w.loss], w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma,
+                    rho_c=w.rho_c, rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=w.max_iters, dtype=w.dtype, n_classes=w.n_classes)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    P.step(w.max_iters)
+    out = P.support(), P.coef(), P.objective()
+    P.close()
+    return out
+
+
+def requests(dtype="f32", K=10):
+    ws = [datagen.batched_instance(r, m, n, dtype=dtype, max_iters=K)
+          for r, m, n in [(0, 900, 70), (1, 1500, 160), (2, 3000, 400), (3, 700, 55)]]
+    sm = datagen.softmax_request(77, m=1200, n=120, C=10, kappa=5, max_iters=K, dtype=dtype)
+    return ws + [sm]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_served_results_match_solo(dtype, tol):
+    bca = _bca()
+    ws = requests(dtype)
+    S = bca.Server(8 << 30, max_slots=8, round_iters=3)
+    tickets = [submit(S, w) for w in ws]
+    st = wait_all(S, tickets)
+    assert all(s == bca.REQ_DONE for s in st), st
+    for w, t in zip(ws, tickets):
+        idx, x, f, lat = S.fetch(t)
+        sidx, sx, sf = solo(w)
+        assert lat > 0
+        assert np.array_equal(idx, sidx), w.name
+        nb = np.linalg.norm(sx)
+        assert np.linalg.norm(x - sx) <= tol * max(nb, 1e-30), w.name
+        assert abs(f - sf) <= tol * abs(sf), w.name
+    S.close()
+
+
+def test_request_alone_equals_in_mix():
+    bca = _bca()
+    ws = requests("f32", K=8)
+    A = bca.Server(8 << 30, max_slots=8, round_iters=2)
+    ta = [submit(A, ws[2]), submit(A, ws[4])]
+    wait_all(A, ta)
+    B = bca.Server(8 << 30, max_slots=8, round_iters=2)
+    tb = [submit(B, w) for w in ws]
+    wait_all(B, tb)
+    for x, y in ((ta[0], tb[2]), (ta[1], tb[4])):
+        ia, xa, fa, _ = A.fetch(x)
+        ib, xb, fb, _ = B.fetch(y)
+        assert np.array_equal(ia, ib) and np.array_equal(xa, xb) and fa == fb
+    A.close()
+    B.close()
+
+
+def test_budget_slots_and_cancel():
+    bca = _bca()
+    ws = requests("f32", K=30)
+    with pytest.raises(bca.BcaError) as e:
+        tiny = bca.Server(1 << 20, max_slots=4, round_iters=1)
+        submit(tiny, ws[2])
+    assert e.value.code == -6
+    tiny.close()
+    S = bca.Server(8 << 30, max_slots=1, round_iters=1)
+    tickets = [submit(S, w) for w in ws[:3]]
+    S.cancel(tickets[2])
+    st = wait_all(S, tickets)
+    assert st[0] == bca.REQ_DONE and st[1] == bca.REQ_DONE and st[2] == bca.REQ_CANCELLED
+    with pytest.raises(bca.BcaError) as e:
+        S.fetch(tickets[2])
+    assert e.value.code == -8
+    assert S.stats()["running"] == 0
+    S.close()

@@ -40,6 +40,11 @@ def workload(name):
         return datagen.config0()
     if name.startswith("slogr_small"):
         return datagen.config1(N=8, m_per=5000, n=1000, kappa=20)
+    if name == "slinr_8x50000x5000_f32":
+        # the same shape with the squared loss (closed-form prox)
+        return datagen.linear_workload(1, N=8, m_per=50000, n=5000, kappa=50, k_true=50,
+                                       noise=0.1, n_blocks=4, dtype="f32", max_iters=100,
+                                       name=name)
     raise SystemExit("unknown workload " + name)
 
 
@@ -81,6 +86,172 @@ def oracle_baseline(w, max_parts=2):
                       % (w.inner_iters, len(parts), w.N, w.N, tx + tg)}
 
 
+def make_problem(bca, w):
+    P = bca.Problem({0: "squared", 1: "logistic", 2: "softmax"}[w.loss], w.n, w.rows, w.n_blocks,
+                    w.kappa, gamma=w.gamma, rho_c=w.rho_c, rho_b=w.rho_b, rho_l=w.rho_l,
+                    inner_iters=w.inner_iters, max_iters=w.max_iters, dtype=w.dtype,
+                    n_classes=w.n_classes)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    return P
+
+
+def batched_bench(args):
+    """Many uneven problems (sizes log-uniform in m in [500, 20000], n in [50, 2000];
+    half squared, half logistic; FP32; 4 partitions x 2 blocks) solved for
+    `iters` outer iterations each in one persistent launch, tile shapes from the
+    autotuner."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    t = time.perf_counter()
+    ms, ns = datagen.config3_sizes(3, args.instances)
+    ws = [datagen.batched_instance(r, int(ms[r]), int(ns[r]), max_iters=args.iters)
+          for r in range(args.instances)]
+    log("generated %d instances in %.1f s" % (len(ws), time.perf_counter() - t))
+    t = time.perf_counter()
+    probs = [make_problem(bca, w) for w in ws]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    log("setup of %d problems %.1f s" % (len(ws), setup_s))
+    t = time.perf_counter()
+    bca.batch_autotune(probs)
+    tune_s = time.perf_counter() - t
+    shapes = {}
+    for P in probs:
+        shapes[str(P.batch_shape())] = shapes.get(str(P.batch_shape()), 0) + 1
+    log("autotune %.1f s, shapes %s" % (tune_s, shapes))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bca.batch_solve(probs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    a_bytes = sum(sum(w.rows) * w.n * 4 for w in ws)
+    fac_bytes = 0
+    for w in ws:
+        for j in range(w.n_blocks):
+            nj = w.n // w.n_blocks + (1 if j < w.n % w.n_blocks else 0)
+            fac_bytes += w.N * nj * (nj + 1) * 8
+    inner = args.iters * ws[0].inner_iters
+    gbps = (a_bytes + fac_bytes) * inner / el / 1e9
+    its = [P.residuals()[3] for P in probs]
+    for P in probs:
+        P.close()
+    out = {"metric": "batched solves/s + ADMM iter/s + HBM GB/s", "value": len(ws) / el,
+           "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": el * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "batched_%d_instances" % len(ws), "iters": args.iters,
+                      "inner_iters": ws[0].inner_iters, "N": 4, "M": 2,
+                      "sum_A_GB": a_bytes / 1e9},
+           "admm_iter_per_s": sum(its) / el,
+           "hbm_gbps_algorithmic": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
+           "setup_s": setup_s, "autotune_s": tune_s, "shapes": shapes}
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Continuous batching on a Poisson trace versus the plain one-at-a-time method
+    on the same trace.  Requests: 80% sparse-fit problems of the batched size
+    distribution (even: squared, odd: logistic), 20% softmax (C = 10, n = 1000,
+    m = 20,000, 30 nonzero rows); each runs `iters` outer iterations."""
+    import threading
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    R = args.requests
+    kind = datagen.uniform_vector(4, datagen.S_KIND, R) < 0.2
+    ms, ns = datagen.instance_sizes(4, R)
+    t = time.perf_counter()
+    ws = []
+    for r in range(R):
+        if kind[r]:
+            ws.append(datagen.softmax_request(4000 + r, max_iters=args.iters))
+        else:
+            ws.append(datagen.batched_instance(r, int(ms[r]), int(ns[r]), base_seed=4000,
+                                               max_iters=args.iters))
+    log("generated %d requests (%d softmax) in %.1f s" % (R, int(kind.sum()), time.perf_counter() - t))
+
+    def plain_solve(w):
+        P = make_problem(bca, w)
+        P.step(w.max_iters)
+        out = P.support(), P.coef(), P.objective()
+        P.close()
+        return out
+
+    # calibration: plain one-at-a-time solves/s on the first requests, back to back
+    ncal = min(20, R)
+    plain_solve(ws[0])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for w in ws[:ncal]:
+        plain_solve(w)
+    plain_rate = ncal / (time.perf_counter() - t)
+    lam = 1.5 * plain_rate
+    gaps = -np.log(datagen.uniform_vector(4, datagen.S_ARRIVAL, R)) / lam
+    release = np.cumsum(gaps)
+    log("plain %.2f solves/s; offered rate %.2f req/s" % (plain_rate, lam))
+
+    # plain method on the trace: one FIFO worker
+    lat_plain = np.zeros(R)
+    t0 = time.perf_counter()
+    for r, w in enumerate(ws):
+        now = time.perf_counter() - t0
+        if now < release[r]:
+            time.sleep(release[r] - now)
+        plain_solve(w)
+        lat_plain[r] = time.perf_counter() - t0 - release[r]
+    span_plain = time.perf_counter() - t0
+    log("plain trace done in %.1f s" % span_plain)
+
+    # served on the same trace
+    S = bca.Server(64 << 30, max_slots=256, round_iters=5)
+    tickets = [None] * R
+    t0 = time.perf_counter()
+
+    def submitter():
+        for r, w in enumerate(ws):
+            now = time.perf_counter() - t0
+            if now < release[r]:
+                time.sleep(release[r] - now)
+            tickets[r] = S.submit({0: "squared", 1: "logistic", 2: "softmax"}[w.loss], w.A, w.b,
+                                  w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
+                                  rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                                  max_iters=w.max_iters, dtype=w.dtype, n_classes=w.n_classes)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat_srv = np.zeros(R)
+    done = np.zeros(R, dtype=bool)
+    while not done.all():
+        for r in range(R):
+            if not done[r] and S.poll(tickets[r]) in (bca.REQ_DONE, bca.REQ_FAILED, bca.REQ_CANCELLED):
+                lat_srv[r] = S.fetch(tickets[r])[3]
+                done[r] = True
+        time.sleep(0.002)
+    span_srv = time.perf_counter() - t0
+    stats = S.stats()
+    S.close()
+    warm = min(100, R // 2) if R >= 200 else 0
+    p = lambda a, q: float(np.percentile(a[warm:], q))
+    out = {"metric": "served solves/s + p99 latency vs plain", "value": R / span_srv,
+           "unit": "solves/s", "n_gpus": 1, "steps": R, "warmup": warm,
+           "ms_per_step": span_srv / R * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serve_%d_requests_poisson" % R, "offered_rate": lam,
+                      "softmax_fraction": float(kind.mean()), "iters": args.iters,
+                      "hbm_budget_GiB": 64, "max_slots": 256, "round_iters": 5},
+           "served": {"solves_per_s": R / span_srv, "p50_s": p(lat_srv, 50), "p99_s": p(lat_srv, 99)},
+           "plain": {"solves_per_s": R / span_plain, "p50_s": p(lat_plain, 50),
+                     "p99_s": p(lat_plain, 99), "calibration_solves_per_s": plain_rate},
+           "server_rounds": stats["rounds"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +261,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve"],
+                    help="plain: one problem (default); batched: many uneven problems in one "
+                         "persistent launch; serve: continuous batching on a Poisson trace")
+    ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the partitions of this build live in one GPU's "
@@ -111,6 +288,10 @@ def main():
         print(json.dumps({"copy_bytes": n * 4}), flush=True)
         return
     import paper_2405_16267_amd as bca
+    if args.mode == "batched":
+        return batched_bench(args)
+    if args.mode == "serve":
+        return serve_bench(args)
 
     t = time.perf_counter()
     w = workload(args.workload)

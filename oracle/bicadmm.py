@@ -267,11 +267,14 @@ class BiCADMM:
     the sparsity counts rows."""
 
     def __init__(self, A_parts, b_parts, loss: int, n_blocks: int, kappa: int, gamma: float,
-                 rho_c: float, rho_b: float, rho_l: float, n_classes: int = 1):
+                 rho_c: float, rho_b: float, rho_l: float, n_classes: int = 1,
+                 n_partitions: Optional[int] = None):
+        """n_partitions: the problem's N when only some partitions' data are given
+        (x-updates are then run for those partitions only)."""
         self.A = [np.asarray(A, dtype=np.float64) for A in A_parts]
         self.b = [np.asarray(b) for b in b_parts]
         self.loss = loss
-        self.N = len(self.A)
+        self.N = len(self.A) if n_partitions is None else n_partitions
         self.n = self.A[0].shape[1]
         self.M = n_blocks
         self.kappa = kappa

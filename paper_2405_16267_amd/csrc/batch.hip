@@ -21,7 +21,8 @@
 //
 // Stream tile shapes: chunks per lane NC (a row of nvec 16-byte chunks is read by
 // one wavefront, NC = ceil(nvec / 64) rounded up to 1, 2, 4 or 8) and rows per
-// wave tile R in {1, 2, 4} (R NC <= 16); rows per item is a runtime parameter.
+// wave tile R in {1, 2, 4} with R NC <= 8, which bounds the kernel's register
+// footprint; rows per item is a runtime parameter.
 // The shape of each problem is picked by the autotuner in bca_api.hip.
 #include <hip/hip_cooperative_groups.h>
 
@@ -37,8 +38,9 @@ constexpr int BT = 256;
 constexpr int BW = BT / 64;
 constexpr int NJ_MAX = 1024;  // largest block width of a batched problem
 
-static const int kShapeNC[11] = {1, 1, 1, 2, 2, 2, 4, 4, 4, 8, 8};
-static const int kShapeR[11] = {1, 2, 4, 1, 2, 4, 1, 2, 4, 1, 2};
+constexpr int kShapes = 9;
+static const int kShapeNC[kShapes] = {1, 1, 1, 2, 2, 2, 4, 4, 8};
+static const int kShapeR[kShapes] = {1, 2, 4, 1, 2, 4, 1, 2, 1};
 
 int batch_max_nvec() { return 64 * 8; }
 
@@ -46,7 +48,7 @@ int batch_shape_code(int nvec, int R) {
   int nc = 1;
   while (nc < 8 && 64 * nc < nvec) nc *= 2;
   if (64 * nc < nvec) return -1;
-  for (int c = 0; c < 11; ++c)
+  for (int c = 0; c < kShapes; ++c)
     if (kShapeNC[c] == nc && kShapeR[c] == R) return c;
   return -1;
 }
@@ -151,15 +153,13 @@ __device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, in
     case 5: stream_item<T, 2, 4>(I, part, chunk, mode); break;
     case 6: stream_item<T, 4, 1>(I, part, chunk, mode); break;
     case 7: stream_item<T, 4, 2>(I, part, chunk, mode); break;
-    case 8: stream_item<T, 4, 4>(I, part, chunk, mode); break;
-    case 9: stream_item<T, 8, 1>(I, part, chunk, mode); break;
-    default: stream_item<T, 8, 2>(I, part, chunk, mode); break;
+    default: stream_item<T, 8, 1>(I, part, chunk, mode); break;
   }
 }
 
 // x_ij-step of one block: rhs = rho_l sum_w gpart_w + rho_c (z - u) - shift x,
 // y = W rhs, x += W^T y (W = L^-1, packed rows / packed columns).
-__device__ void solve_item(const BatchInst& I, int part, int blk, double* rs, double* ys) {
+__device__ __noinline__ void solve_item(const BatchInst& I, int part, int blk, double* rs, double* ys) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
@@ -227,6 +227,13 @@ __device__ void solve_item(const BatchInst& I, int part, int blk, double* rs, do
     }
     __syncthreads();
   }
+}
+
+// Out of line, with 7 multisection points per round, so that the global step's
+// registers do not add to those of the streaming items.
+__device__ __noinline__ void global_step_batched(const GlobalArgs& g, double* shd,
+                                                 TopkShared<BT>& tks) {
+  global_step<BT, 7>(g, shd, tks);
 }
 
 __device__ GlobalArgs global_args_of(const BatchInst& I) {
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs ba) {
     for (int it = claim(); it < ba.count; it = claim()) {
       const BatchInst& I = ba.inst[it];
       if (o >= I.outer) continue;
-      global_step<BT>(global_args_of(I), shd, tks);
+      global_step_batched(global_args_of(I), shd, tks);
       __syncthreads();
     }
     ++phase;

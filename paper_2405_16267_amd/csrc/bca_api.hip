@@ -867,7 +867,10 @@ struct BatchContext {
 };
 BatchContext g_batch;
 
-int batch_rows_tile(bca_problem P) { return P->b_rows_tile > 0 ? P->b_rows_tile : 2; }
+int batch_rows_tile(bca_problem P) {
+  if (P->b_rows_tile > 0) return P->b_rows_tile;
+  return batch_shape_code(P->nvec, 2) >= 0 ? 2 : 1;
+}
 int batch_rows_item(bca_problem P) { return P->b_rows_item > 0 ? P->b_rows_item : 512; }
 
 int batch_check(bca_problem P) {

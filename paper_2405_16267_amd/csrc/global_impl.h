@@ -158,9 +158,9 @@ __device__ void topk_apply(const Z* z, int64_t n, uint64_t thr, int take_eq, Top
   }
 }
 
-// One global step with a workgroup of BT threads; shd holds (BT / 64) * (PSECT + 2)
-// doubles of shared memory.
-template <int BT>
+// One global step with a workgroup of BT threads, PS interior points per
+// multisection round; shd holds (BT / 64) * (PSECT + 2) doubles of shared memory.
+template <int BT, int PS = PSECT>
 __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tks) {
   constexpr int GT = BT;
   const int n = a.n, N = a.N, C = a.C;
@@ -217,28 +217,28 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
   } else {
     double lo = 0.0, hi = hi0;
     for (int round = 0; round < 200; ++round) {
-      double acc[PSECT + 1];
-      double pts[PSECT];
+      double acc[PS + 1];
+      double pts[PS];
 #pragma unroll
-      for (int p = 0; p < PSECT; ++p) {
-        pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PSECT + 1);
+      for (int p = 0; p < PS; ++p) {
+        pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PS + 1);
         acc[p] = 0.0;
       }
-      acc[PSECT] = 0.0;  // breakpoints strictly inside (lo, hi)
+      acc[PS] = 0.0;  // breakpoints strictly inside (lo, hi)
       for (int k = tid; k < n; k += GT) {
         const double t = th[k];
         const double ca = c1[k], cb = c2[k];
 #pragma unroll
-        for (int p = 0; p < PSECT; ++p)
+        for (int p = 0; p < PS; ++p)
           if (t > pts[p]) acc[p] += pts[p] * cb - ca;
-        if (t > lo && t < hi) acc[PSECT] += 1.0;
+        if (t > lo && t < hi) acc[PS] += 1.0;
       }
-      block_sum_n<BT, PSECT + 1>(acc, shd);
-      if (acc[PSECT] == 0.0) break;
+      block_sum_n<BT, PS + 1>(acc, shd);
+      if (acc[PS] == 0.0) break;
       int p = 0;
-      while (p < PSECT && v + pts[p] / rb + acc[p] < 0.0) ++p;
+      while (p < PS && v + pts[p] / rb + acc[p] < 0.0) ++p;
       const double nlo = p == 0 ? lo : pts[p - 1];
-      const double nhi = p == PSECT ? hi : pts[p];
+      const double nhi = p == PS ? hi : pts[p];
       if (nlo == lo && nhi == hi) break;
       lo = nlo;
       hi = nhi;

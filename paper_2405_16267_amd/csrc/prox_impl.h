@@ -12,12 +12,15 @@ __device__ __forceinline__ double prox_scalar(int loss, double c, double b, int 
   if (loss == BCA_LOSS_SQUARED) return (2.0 * b + rho_l * c) / (2.0 * M + rho_l);
   // Logistic: root of -b sigmoid(-b q) + beta (q - Mc), bracketed in
   // [Mc - 1/beta, Mc + 1/beta]; Newton steps kept inside the bracket by bisection,
-  // until the step is below a few ulp.
+  // until the step is below the rounding level of the derivative, a few ulp of
+  // |q| + |Mc| + 1/beta (a tolerance relative to |q| alone is unreachable when
+  // |q| is much smaller than |q - Mc|).
   const double beta = rho_l / M;
   const double q0 = M * c;
   double lo = q0 - 1.0 / beta, hi = q0 + 1.0 / beta;
   double q = M * w_prev;
   if (!(q > lo && q < hi)) q = q0;
+  const double tol = 4.0 * 2.220446049250313e-16 * (fabs(q0) + 1.0 / beta);
   for (int it = 0; it < 100; ++it) {
     const double sg = 1.0 / (1.0 + exp(b * q));  // sigmoid(-b q)
     const double g = -b * sg + beta * (q - q0);
@@ -26,8 +29,8 @@ __device__ __forceinline__ double prox_scalar(int loss, double c, double b, int 
     const double h = sg * (1.0 - sg) + beta;
     double qn = q - g / h;
     if (!(qn > lo && qn < hi)) qn = 0.5 * (lo + hi);
-    const double tol = 4.0 * 2.220446049250313e-16 * fabs(q);
-    const bool done = fabs(qn - q) <= tol || (hi - lo) <= tol;
+    const double t = tol + 4.0 * 2.220446049250313e-16 * fabs(q);
+    const bool done = fabs(qn - q) <= t || (hi - lo) <= t;
     q = qn;
     if (done) break;
   }

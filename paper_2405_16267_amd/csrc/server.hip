@@ -191,7 +191,10 @@ void scheduler(bca_server_s* S) {
     for (Request* r : act) {
       if (r->cancel) continue;
       if (r->params.loss == BCA_LOSS_SOFTMAX) {
-        if (bca_step(r->prob, S->round_iters, nullptr) != BCA_OK) failed.push_back({r, bca_last_error()});
+        int done_it = 0;
+        bca_get_residuals(r->prob, nullptr, nullptr, nullptr, &done_it);
+        const int k = std::min(S->round_iters, r->params.max_iters - done_it);
+        if (k > 0 && bca_step(r->prob, k, nullptr) != BCA_OK) failed.push_back({r, bca_last_error()});
       } else {
         one_class.push_back(r->prob);
         oc_req.push_back(r);

@@ -24,7 +24,9 @@
 
 namespace bca {
 
-template <typename T, int NT, int NC, int R>
+// LACC: keep the FP64 partial sums of A^T e in LDS instead of registers (for
+// 8-element BF16 chunks, whose register footprint would otherwise halve occupancy).
+template <typename T, int NT, int NC, int R, bool LACC>
 __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
   using TR = Traits<T>;
   using V = typename TR::vec_t;
@@ -33,6 +35,7 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
   constexpr int NW = NT / 64;
   __shared__ double red[NW][R];
   __shared__ double e_sh[R];
+  __shared__ double gsh[LACC ? NC * VEC : 1][LACC ? NT : 1];
 
   const int part = blockIdx.x / a.Gp;
   const int wg = blockIdx.x - part * a.Gp;
@@ -48,11 +51,16 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) xr[q][e] = (k < a.nvec) ? xs[k * VEC + e] : acc(0);
   }
-  double g[NC][VEC];
+  double g[LACC ? 1 : NC][LACC ? 1 : VEC];
+  if constexpr (LACC) {
 #pragma unroll
-  for (int q = 0; q < NC; ++q)
+    for (int q = 0; q < NC * VEC; ++q) gsh[q][tid] = 0.0;
+  } else {
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) g[q][e] = 0.0;
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) g[q][e] = 0.0;
+  }
 
   const T* Ab = reinterpret_cast<const T*>(a.A) + r0 * a.ld;
   const int64_t ntiles = (m + R - 1) / R;
@@ -122,7 +130,10 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
         acc t = acc(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) t += er[r] * vget(v[r][q], e);
-        g[q][e] += (double)t;
+        if constexpr (LACC)
+          gsh[q * VEC + e][tid] += (double)t;
+        else
+          g[q][e] += (double)t;
       }
   }
   double* gp = a.gpart + ((int64_t)part * a.Gp + wg) * a.ld;
@@ -131,7 +142,12 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
     const int k = tid + q * NT;
     if (k < a.nvec) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) gp[k * VEC + e] = g[q][e];
+      for (int e = 0; e < VEC; ++e) {
+        if constexpr (LACC)
+          gp[k * VEC + e] = gsh[q * VEC + e][tid];
+        else
+          gp[k * VEC + e] = g[q][e];
+      }
     }
   }
 }
@@ -189,21 +205,25 @@ __global__ __launch_bounds__(NT) void objective_kernel(ObjArgs a) {
   if (tid == 0) a.partial[blockIdx.x] = lsum;
 }
 
-#define BCA_STREAM_NC_CASES(T, NT)                                                              \
-  switch (nc) {                                                                                 \
-    case 1: hipLaunchKernelGGL((stream_kernel<T, NT, 1, RT>), grid, dim3(NT), 0, s, a); break;  \
-    case 2: hipLaunchKernelGGL((stream_kernel<T, NT, 2, RT>), grid, dim3(NT), 0, s, a); break;  \
-    case 3: hipLaunchKernelGGL((stream_kernel<T, NT, 3, RT>), grid, dim3(NT), 0, s, a); break;  \
-    case 4: hipLaunchKernelGGL((stream_kernel<T, NT, 4, RT>), grid, dim3(NT), 0, s, a); break;  \
-    case 5: hipLaunchKernelGGL((stream_kernel<T, NT, 5, RT>), grid, dim3(NT), 0, s, a); break;  \
-    case 6: hipLaunchKernelGGL((stream_kernel<T, NT, 6, RT>), grid, dim3(NT), 0, s, a); break;  \
-    default: hipLaunchKernelGGL((stream_kernel<T, NT, 8, RT>), grid, dim3(NT), 0, s, a); break; \
+#define BCA_STREAM_NC_CASES(T, NT, RT)                                                           \
+  switch (nc) {                                                                                   \
+    case 1: hipLaunchKernelGGL((stream_kernel<T, NT, 1, RT, use_lacc<T, NT, 1>()>), grid, dim3(NT), 0, s, a); break;    \
+    case 2: hipLaunchKernelGGL((stream_kernel<T, NT, 2, RT, use_lacc<T, NT, 2>()>), grid, dim3(NT), 0, s, a); break;    \
+    case 3: hipLaunchKernelGGL((stream_kernel<T, NT, 3, RT, use_lacc<T, NT, 3>()>), grid, dim3(NT), 0, s, a); break;    \
+    case 4: hipLaunchKernelGGL((stream_kernel<T, NT, 4, RT, use_lacc<T, NT, 4>()>), grid, dim3(NT), 0, s, a); break;    \
+    case 5: hipLaunchKernelGGL((stream_kernel<T, NT, 5, RT, use_lacc<T, NT, 5>()>), grid, dim3(NT), 0, s, a); break;    \
+    case 6: hipLaunchKernelGGL((stream_kernel<T, NT, 6, RT, use_lacc<T, NT, 6>()>), grid, dim3(NT), 0, s, a); break;    \
+    default: hipLaunchKernelGGL((stream_kernel<T, NT, 8, RT, use_lacc<T, NT, 8>()>), grid, dim3(NT), 0, s, a); break;   \
   }
 
-// Threads per workgroup and chunks per thread for a row of nvec chunks.
+// Threads per workgroup and 16-byte chunks per thread for a row of nvec chunks:
+// up to 6 chunks per thread with 256 threads, then 512 threads (still up to 256
+// VGPRs per lane), then 1024.
 static void stream_shape(int nvec, int* nt, int* nc) {
   if (nvec <= 6 * 256) {
     *nt = 256;
+  } else if (nvec <= 6 * 512) {
+    *nt = 512;
   } else {
     *nt = 1024;
   }
@@ -212,18 +232,37 @@ static void stream_shape(int nvec, int* nt, int* nc) {
   *nc = c < 1 ? 1 : c;
 }
 
-static constexpr int RT = 4;  // rows per tile
+// Rows per tile and where the FP64 partial sums live (LDS for BF16 when they fit
+// in 96 KB, so that a CU still holds more than one workgroup).
+template <typename T>
+struct StreamRows {
+  static constexpr int R = 4;
+  static constexpr bool LACC = false;
+};
+template <>
+struct StreamRows<bf16_t> {
+  static constexpr int R = 2;
+  static constexpr bool LACC = true;
+};
+
+template <typename T, int NT, int NC>
+constexpr bool use_lacc() {
+  return StreamRows<T>::LACC && NC * Traits<T>::VEC * NT * 8 <= 96 * 1024;
+}
 
 template <typename T>
 static hipError_t stream_dispatch(const StreamArgs& a, hipStream_t s) {
+  constexpr int RT = StreamRows<T>::R;
   int nt, nc;
   stream_shape(a.nvec, &nt, &nc);
   if (nc > 8) return hipErrorInvalidValue;
   dim3 grid(a.N * a.Gp);
   if (nt == 256) {
-    BCA_STREAM_NC_CASES(T, 256)
+    BCA_STREAM_NC_CASES(T, 256, RT)
+  } else if (nt == 512) {
+    BCA_STREAM_NC_CASES(T, 512, RT)
   } else {
-    BCA_STREAM_NC_CASES(T, 1024)
+    BCA_STREAM_NC_CASES(T, 1024, RT)
   }
   return hipGetLastError();
 }
@@ -237,38 +276,34 @@ hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s) {
   }
 }
 
-template <typename T>
-static int occ_one(int nvec) {
-  int nt, nc;
-  stream_shape(nvec, &nt, &nc);
+template <typename T, int NT>
+static int occ_nt(int nc) {
+  constexpr int RT = StreamRows<T>::R;
   int blocks = 0;
   hipError_t e = hipSuccess;
-#define BCA_OCC(NT_, NC_) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stream_kernel<T, NT_, NC_, RT>, NT_, 0)
-  if (nt == 256) {
-    switch (nc) {
-      case 1: BCA_OCC(256, 1); break;
-      case 2: BCA_OCC(256, 2); break;
-      case 3: BCA_OCC(256, 3); break;
-      case 4: BCA_OCC(256, 4); break;
-      case 5: BCA_OCC(256, 5); break;
-      case 6: BCA_OCC(256, 6); break;
-      default: BCA_OCC(256, 8); break;
-    }
-  } else {
-    switch (nc) {
-      case 1: BCA_OCC(1024, 1); break;
-      case 2: BCA_OCC(1024, 2); break;
-      case 3: BCA_OCC(1024, 3); break;
-      case 4: BCA_OCC(1024, 4); break;
-      case 5: BCA_OCC(1024, 5); break;
-      case 6: BCA_OCC(1024, 6); break;
-      default: BCA_OCC(1024, 8); break;
-    }
+#define BCA_OCC(NC_) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stream_kernel<T, NT, NC_, RT, use_lacc<T, NT, NC_>()>, NT, 0)
+  switch (nc) {
+    case 1: BCA_OCC(1); break;
+    case 2: BCA_OCC(2); break;
+    case 3: BCA_OCC(3); break;
+    case 4: BCA_OCC(4); break;
+    case 5: BCA_OCC(5); break;
+    case 6: BCA_OCC(6); break;
+    default: BCA_OCC(8); break;
   }
 #undef BCA_OCC
   if (e != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
+}
+
+template <typename T>
+static int occ_one(int nvec) {
+  int nt, nc;
+  stream_shape(nvec, &nt, &nc);
+  if (nt == 256) return occ_nt<T, 256>(nc);
+  if (nt == 512) return occ_nt<T, 512>(nc);
+  return occ_nt<T, 1024>(nc);
 }
 
 int stream_occupancy_workgroups(int dtype, int nvec, int C) {
@@ -295,6 +330,16 @@ static hipError_t objective_dispatch(const ObjArgs& a, hipStream_t s) {
       case 5: BCA_OBJ(256, 5); break;
       case 6: BCA_OBJ(256, 6); break;
       default: BCA_OBJ(256, 8); break;
+    }
+  } else if (nt == 512) {
+    switch (nc) {
+      case 1: BCA_OBJ(512, 1); break;
+      case 2: BCA_OBJ(512, 2); break;
+      case 3: BCA_OBJ(512, 3); break;
+      case 4: BCA_OBJ(512, 4); break;
+      case 5: BCA_OBJ(512, 5); break;
+      case 6: BCA_OBJ(512, 6); break;
+      default: BCA_OBJ(512, 8); break;
     }
   } else {
     switch (nc) {

@@ -14,7 +14,8 @@
 // steps whose Hessian diag(p) - p p^T + beta I is inverted by Sherman-Morrison
 // (D = diag(p + beta)): H^-1 g = D^-1 g + D^-1 p (p^T D^-1 g) / (1 - p^T D^-1 p),
 // with backtracking (Armijo on F, or a decrease of ||grad|| once F is flat to
-// rounding) until ||grad|| <= 1e-14; omega-bar = q / M.
+// rounding) until ||grad|| <= 1e-14 (or the rounding level of beta (q - Mc) when
+// that is higher); omega-bar = q / M.
 #include "bca_internal.h"
 
 namespace bca {
@@ -73,9 +74,14 @@ __device__ void prox_softmax_row(const double* cvec, const double* w_prev, int y
     q0[c] = M * cvec[c];
     q[c] = M * w_prev[c];
   }
+  // stop at ||grad|| <= 1e-14, or at the rounding level of beta (q - Mc) if higher
+  double qmax = 0.0;
+  for (int c = 0; c < C; ++c) qmax = fmax(qmax, fabs(q0[c]));
   for (int it = 0; it < 100; ++it) {
     const double gn = softmax_grad(q, q0, y, beta, C, p, g);
-    if (!(gn > 1e-14)) break;
+    double qa = qmax;
+    for (int c = 0; c < C; ++c) qa = fmax(qa, fabs(q[c]));
+    if (!(gn > 1e-14 + 8.0 * 2.220446049250313e-16 * beta * 2.0 * qa)) break;
     double pDp = 0.0, pDg = 0.0;
     for (int c = 0; c < C; ++c) {
       const double d = 1.0 / (p[c] + beta);

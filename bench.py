@@ -14,6 +14,8 @@ the FP64 oracle timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +32,36 @@ FP64_PEAK_TFLOPS = 78.6
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+# Sources that define the A-streaming kernel; counter-based traffic figures are
+# only reported for the exact source they were taken on.
+STREAM_SOURCES = ("paper_2405_16267_amd/csrc/stream.hip", "paper_2405_16267_amd/csrc/prox_impl.h",
+                  "paper_2405_16267_amd/csrc/bca_internal.h")
+
+
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, workload_name, src_hash):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summaries
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the plain-copy calibration),
+    or None when no summary was taken on the current kernel source."""
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+                if (kv.get("kernel") == kernel and kv.get("workload") == workload_name
+                        and kv.get("source") == src_hash):
+                    return float(kv["read_bytes"]) + float(kv["write_bytes"]), os.path.basename(path)
+    return None, None
 
 
 def workload(name):
@@ -152,6 +184,94 @@ def batched_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def precision_bench(args):
+    """Precision form: sparse linear regression on 16 partitions of 100,000 x 10,000
+    (A iid N(0,1), unit-norm columns per partition, planted 100-sparse +-U(1,2)
+    model, noise 0.05, kappa = 100, 4 feature blocks), stored as BF16 and, beside
+    it on the same GPU, as the canonical FP32 matrix the BF16 values were rounded
+    from.  Both forms run the same iterations; reported: iter/s and the streaming
+    roofline of each, the Gram's MFMA utilisation for each dtype, and the BF16
+    result's deviation from the FP32 result with the first-order BF16 bound
+    4 cond(K) 2^-8 (cond of feature block 0 of partition 0, from its factor)."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    N, m, n, kappa, Mb = 16, args.m_per or 100000, 10000 if not args.m_per else max(1000, args.m_per // 10), 100, 4
+    supp, val = datagen.linear_model(2, n, kappa)
+    rows = [m] * N
+    kw = dict(gamma=10.0, rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5,
+              max_iters=args.warmup + args.steps)
+    Pb = bca.Problem("squared", n, rows, Mb, kappa, dtype="bf16", **kw)
+    P32 = bca.Problem("squared", n, rows, Mb, kappa, dtype="f32", **kw)
+    t = time.perf_counter()
+    for i in range(N):
+        (A32, Abf), b = datagen.linear_partition(2, i, m, n, supp, val, 0.05, "f32+bf16", True)
+        Pb.set_data(i, Abf, b)
+        P32.set_data(i, A32, b)
+        del A32, Abf, b
+        log("partition %d of %d resident (%.1f s)" % (i + 1, N, time.perf_counter() - t))
+    bounds = [(n // Mb + (1 if j < n % Mb else 0)) for j in range(Mb)]
+    gram_flops = sum(m * nj * (nj + 1) for nj in bounds) * N
+    res = {}
+    for name, P, esize, peak in (("bf16", Pb, 2, BF16_MFMA_PEAK_TFLOPS),
+                                 ("f32", P32, 4, FP32_MFMA_PEAK_TFLOPS)):
+        P.set_timing(True)
+        t = time.perf_counter()
+        P.finalize()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        n_gram, gram_ms = P.timing(bca.KC_GRAM)
+        n_fac, fac_ms = P.timing(bca.KC_FACTOR)
+        P.set_timing(False)
+        P.step(args.warmup)
+        torch.cuda.synchronize()
+        P.set_timing(True)
+        t0 = time.perf_counter()
+        P.step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n_st, st_ms = P.timing(bca.KC_STREAM)
+        n_so, so_ms = P.timing(bca.KC_SOLVE)
+        n_gl, gl_ms = P.timing(bca.KC_GLOBAL)
+        stream_bytes = N * m * n * esize + 32 * N * m
+        avg_s = st_ms / max(n_st, 1) / 1e3
+        ach = stream_bytes / avg_s / 1e9
+        gtf = gram_flops / (gram_ms / 1e3) / 1e12 if gram_ms > 0 else None
+        log("%s: %.2f iter/s, stream %.3f ms (%.0f GB/s), gram %.1f ms" % (name, args.steps / el, avg_s * 1e3, ach, gram_ms))
+        res[name] = {"iter_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
+                     "roofline": {"bound": "hbm", "kernel": "stream_kernel", "achieved": ach,
+                                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+                                  "bytes_per_launch": stream_bytes, "avg_launch_ms": avg_s * 1e3,
+                                  "launches": n_st},
+                     "kernels_ms_per_step": {"stream": st_ms / args.steps, "solve": so_ms / args.steps,
+                                             "global": gl_ms / args.steps},
+                     "setup": {"seconds": setup_s, "gram_ms": gram_ms, "factor_ms": fac_ms,
+                               "gram_tflops": gtf, "gram_mfma_peak_tflops": peak,
+                               "gram_mfma_frac": gtf / peak if gtf else None}}
+    xb, x32 = Pb.coef(), P32.coef()
+    fb, f32 = Pb.objective(), P32.objective()
+    same_support = bool(np.array_equal(Pb.support(), P32.support()))
+    W = P32.factor(0, 0)
+    sv = np.linalg.svd(W, compute_uv=False)
+    condK = float((sv[0] / sv[-1]) ** 2)
+    Pb.close()
+    P32.close()
+    err = float(np.linalg.norm(xb - x32) / np.linalg.norm(x32))
+    out = {"metric": "ADMM iter/s + HBM GB/s (precision form, BF16 beside FP32)",
+           "value": res["bf16"]["iter_per_s"], "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["bf16"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": "slinr_%dx%dx%d_bf16_beside_f32" % (N, m, n), "N": N,
+                      "m_per_partition": m, "n": n, "M": Mb, "kappa": kappa, "inner_iters": 5},
+           "bf16": res["bf16"], "f32": res["f32"],
+           "bf16_vs_f32": {"coef_rel": err, "objective_rel": abs(fb - f32) / abs(f32),
+                           "same_support": same_support, "cond_K_block0": condK,
+                           "first_order_bound": 4 * condK * 2.0 ** -8}}
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Continuous batching on a Poisson trace versus the plain one-at-a-time method
     on the same trace.  Requests: 80% sparse-fit problems of the batched size
@@ -261,12 +381,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve", "precision"],
                     help="plain: one problem (default); batched: many uneven problems in one "
-                         "persistent launch; serve: continuous batching on a Poisson trace")
+                         "persistent launch; serve: continuous batching on a Poisson trace; precision: "
+                         "BF16 beside FP32 at 16 x 100,000 x 10,000")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
+    ap.add_argument("--m-per", type=int, default=0,
+                    help="precision: rows per partition (default 100,000; smaller values shrink n too)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the partitions of this build live in one GPU's "
@@ -292,6 +415,8 @@ def main():
         return batched_bench(args)
     if args.mode == "serve":
         return serve_bench(args)
+    if args.mode == "precision":
+        return precision_bench(args)
 
     t = time.perf_counter()
     w = workload(args.workload)
@@ -343,6 +468,8 @@ def main():
     factor_bytes = w.N * sum(nj * (nj + 1) * 8 for nj in bounds)
     inner_bytes = stream_bytes + factor_bytes
     ms_per_step = elapsed / args.steps * 1e3
+    src_hash = source_hash(STREAM_SOURCES)
+    traffic, traffic_file = counter_traffic("stream_kernel", w.name, src_hash)
     gram_flops = sum(m * nj * (nj + 1) for m in w.rows for nj in bounds)
     gram_peak = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_MFMA_PEAK_TFLOPS, "bf16": BF16_MFMA_PEAK_TFLOPS}[w.dtype]
     gram_tflops = gram_flops / (gram_ms / 1e3) / 1e12 if gram_ms > 0 else None
@@ -367,7 +494,9 @@ def main():
         "hbm_gbps_algorithmic": inner_bytes * w.inner_iters * args.steps / elapsed / 1e9,
         "roofline": {"bound": "hbm", "kernel": "stream_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None, "bytes_per_launch": stream_bytes,
+                     "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "traffic_source": traffic_file, "kernel_source": src_hash,
+                     "bytes_per_launch": stream_bytes,
                      "avg_launch_ms": stream_avg_s * 1e3, "launches": n_st},
         "kernels_ms_per_step": {"stream": st_ms / args.steps, "solve": so_ms / args.steps,
                                 "global": gl_ms / args.steps},

@@ -69,12 +69,13 @@ def lib():
         _lib.bcd_ar1_rows.argtypes = [P, i64, i64, i64, dbl]
         _lib.bcd_normalize_columns.argtypes = [P, i64, i64, i64]
         _lib.bcd_to_f32.argtypes = [P, i64, i64, i64, P, i64]
+        _lib.bcd_gaussian_block.argtypes = [u64, u32, i64, i64, i64, ctypes.c_int, P, P, i64]
         _lib.bcd_f32_to_bf16.argtypes = [P, i64, i64, i64, P, i64]
         _lib.bcd_bf16_to_f64.argtypes = [P, i64, i64, i64, P, i64]
         _lib.bcd_sparse_predict_f32.argtypes = [P, i64, i64, P, P, i64, P]
         _lib.bcd_sparse_predict_f64.argtypes = [P, i64, i64, P, P, i64, P]
         for f in ("bcd_philox4x32_10", "bcd_normal_matrix", "bcd_uniform_vector",
-                  "bcd_normal_vector", "bcd_ar1_rows", "bcd_normalize_columns", "bcd_to_f32",
+                  "bcd_normal_vector", "bcd_ar1_rows", "bcd_normalize_columns", "bcd_to_f32", "bcd_gaussian_block",
                   "bcd_f32_to_bf16", "bcd_bf16_to_f64", "bcd_sparse_predict_f32",
                   "bcd_sparse_predict_f64"):
             getattr(_lib, f).restype = None
@@ -204,6 +205,40 @@ def split_rows(m: int, N: int) -> List[int]:
     return [q + (1 if i < r else 0) for i in range(N)]
 
 
+def linear_model(seed: int, n: int, k_true: int):
+    """Planted model of the sparse linear recipe: k_true indices uniform without
+    replacement, values +-U(1,2)."""
+    supp = planted_support(seed, n, k_true)
+    mag = 1.0 + uniform_vector(seed, S_VALUES, k_true)
+    sgn = np.where(uniform_vector(seed, S_SIGNS, k_true) < 0.5, -1.0, 1.0)
+    return supp, sgn * mag
+
+
+def linear_partition(seed: int, i: int, m: int, n: int, supp, val, noise: float,
+                     dtype: str = "f64", normalize: bool = False):
+    """Partition i of the sparse linear recipe: A_i iid N(0,1) (optionally unit-norm
+    columns, normalised in FP64), stored in `dtype` ("f64", "f32", "bf16" bits, or
+    "f32+bf16" for both roundings of the same data); b_i = A_i x* + N(0, noise^2)
+    with A_i the canonical (FP64, else FP32) matrix.  Returns (A, b), A a tuple
+    (A32, Abf16) for "f32+bf16"."""
+    if dtype == "f64":
+        G = normal_matrix(seed, S_A + i, m, n)
+        if normalize:
+            lib().bcd_normalize_columns(_p(G), m, n, n)
+        Ai = Aval = G
+    else:
+        # drawn straight to FP32 (and BF16), normalised with FP64 column sums
+        A32 = np.empty((m, n), dtype=np.float32)
+        Abf = np.empty((m, n), dtype=np.uint16) if dtype != "f32" else None
+        lib().bcd_gaussian_block(seed, S_A + i, m, n, 0, int(normalize), _p(A32),
+                                 _p(Abf) if Abf is not None else None, n)
+        Aval = A32                      # targets use the canonical FP32 matrix
+        Ai = {"f32": A32, "bf16": Abf}.get(dtype, (A32, Abf))
+    pred = sparse_predict(Aval, supp, val)
+    b = pred + noise * normal_vector(seed, S_NOISE + i, m)
+    return Ai, b
+
+
 def linear_workload(seed: int, N: int, m_per, n: int, kappa: int, k_true: int, noise: float,
                     n_blocks: int, dtype: str = "f64", normalize: bool = False,
                     max_iters: int = 200, inner_iters: int = 5, rho: float = 1.0,
@@ -211,27 +246,12 @@ def linear_workload(seed: int, N: int, m_per, n: int, kappa: int, k_true: int, n
     """Sparse linear regression: A_i iid N(0,1) (optionally unit-norm columns per
     partition), planted x* with values +-U(1,2), b_i = A_i x* + N(0, noise^2)."""
     rows = m_per if isinstance(m_per, (list, tuple)) else [m_per] * N
-    supp = planted_support(seed, n, k_true)
-    mag = 1.0 + uniform_vector(seed, S_VALUES, k_true)
-    sgn = np.where(uniform_vector(seed, S_SIGNS, k_true) < 0.5, -1.0, 1.0)
-    val = sgn * mag
+    supp, val = linear_model(seed, n, k_true)
     x_true = np.zeros(n)
     x_true[supp] = val
     A_out, b_out = [], []
     for i, m in enumerate(rows):
-        G = normal_matrix(seed, S_A + i, m, n)
-        if normalize:
-            lib().bcd_normalize_columns(_p(G), m, n, n)
-        if dtype == "f64":
-            Ai = G
-            Aval = G
-        else:
-            A32 = to_f32(G)
-            del G
-            Ai = A32 if dtype == "f32" else f32_to_bf16_bits(A32)
-            Aval = A32                      # targets use the canonical FP32 matrix
-        pred = sparse_predict(Aval, supp, val)
-        b = pred + noise * normal_vector(seed, S_NOISE + i, m)
+        Ai, b = linear_partition(seed, i, m, n, supp, val, noise, dtype, normalize)
         A_out.append(Ai)
         b_out.append(b)
     return Workload(name=name, loss=LOSS_SQUARED, A=A_out, b=b_out, n=n, kappa=kappa,

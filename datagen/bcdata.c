@@ -18,6 +18,7 @@
  * regenerated on its own.  Normals use the Box-Muller transform.
  */
 #include <math.h>
+#include <stdlib.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -153,6 +154,58 @@ void bcd_f32_to_bf16(const float* in, int64_t m, int64_t n, int64_t ld_in, uint1
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < m; ++r)
     for (int64_t c = 0; c < n; ++c) out[r * ld_out + c] = f32_to_bf16_rne(in[r * ld_in + c]);
+}
+
+/* Gaussian block straight to its storage precisions, without an FP64 copy:
+ * out32[r*ld + c] = fp32(z(r, c) * s_c) and, if outbf is given, outbf = bf16 RNE of
+ * that FP32 value, with z the N(0,1) draw at (seed, stream, row0 + r, c).
+ * With normalize set, s_c = 1/||z(., c)||_2 (FP64 sums, column by column over
+ * fixed 256-row chunks whose partial sums are added in chunk order, so the
+ * result does not depend on the thread count); otherwise s_c = 1.  The rows are
+ * drawn twice (once for the norms, once for the output), which the counter-based
+ * generator makes exact. */
+void bcd_gaussian_block(uint64_t seed, uint32_t stream, int64_t m, int64_t n, int64_t row0,
+                        int normalize, float* out32, uint16_t* outbf, int64_t ld) {
+  const int64_t CH = 256;
+  const int64_t nch = (m + CH - 1) / CH;
+  const int64_t nq = (n + 3) / 4;
+  double* scale = (double*)malloc(sizeof(double) * (size_t)(nq * 4));
+  for (int64_t c = 0; c < nq * 4; ++c) scale[c] = 1.0;
+  if (normalize) {
+    double* part = (double*)calloc((size_t)(nch * nq * 4), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nch; ++k) {
+      double* ps = part + k * nq * 4;
+      const int64_t r1 = (k + 1) * CH < m ? (k + 1) * CH : m;
+      for (int64_t r = k * CH; r < r1; ++r)
+        for (int64_t q = 0; q < nq; ++q) {
+          double z[4];
+          normals4(seed, stream, (uint64_t)(row0 + r), (uint32_t)q, z);
+          for (int t = 0; t < 4; ++t) ps[q * 4 + t] += z[t] * z[t];
+        }
+    }
+    for (int64_t c = 0; c < n; ++c) {
+      double ss = 0.0;
+      for (int64_t k = 0; k < nch; ++k) ss += part[k * nq * 4 + c];
+      scale[c] = ss > 0 ? 1.0 / sqrt(ss) : 0.0;
+    }
+    free(part);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < m; ++r) {
+    float* o = out32 + r * ld;
+    uint16_t* ob = outbf ? outbf + r * ld : 0;
+    for (int64_t q = 0; q < nq; ++q) {
+      double z[4];
+      normals4(seed, stream, (uint64_t)(row0 + r), (uint32_t)q, z);
+      for (int t = 0; t < 4 && q * 4 + t < n; ++t) {
+        const float f = (float)(z[t] * scale[q * 4 + t]);
+        o[q * 4 + t] = f;
+        if (ob) ob[q * 4 + t] = f32_to_bf16_rne(f);
+      }
+    }
+  }
+  free(scale);
 }
 
 void bcd_bf16_to_f64(const uint16_t* in, int64_t m, int64_t n, int64_t ld_in, double* out,

@@ -27,10 +27,18 @@ __device__ __forceinline__ double prox_scalar(int loss, double c, double b, int 
     if (g == 0.0) break;
     if (g < 0.0) lo = q; else hi = q;
     const double h = sg * (1.0 - sg) + beta;
-    double qn = q - g / h;
-    if (!(qn > lo && qn < hi)) qn = 0.5 * (lo + hi);
+    const double step = g / h;
     const double t = tol + 4.0 * 2.220446049250313e-16 * fabs(q);
-    const bool done = fabs(qn - q) <= t || (hi - lo) <= t;
+    // A converged step is taken as is: near the root q - step can round to q
+    // itself (the bracket end just set), which the bracket test below would
+    // misread as an overshoot and answer with bisection steps.
+    if (fabs(step) <= t) {
+      q -= step;
+      break;
+    }
+    double qn = q - step;
+    if (!(qn > lo && qn < hi)) qn = 0.5 * (lo + hi);
+    const bool done = (hi - lo) <= t;
     q = qn;
     if (done) break;
   }

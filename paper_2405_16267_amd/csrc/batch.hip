@@ -53,12 +53,16 @@ int batch_shape_code(int nvec, int R) {
   return -1;
 }
 
+// LG: the widest FP32 shape (32 columns per lane) keeps its FP64 partial sums of
+// A^T e in LDS (lg, 32 x BT doubles) instead of 64 registers, which would
+// otherwise set the register budget of the whole persistent kernel.
 template <typename T, int NC, int R>
-__device__ void stream_item(const BatchInst& I, int part, int chunk, int mode) {
+__device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, double* lg) {
   using TR = Traits<T>;
   using V = typename TR::vec_t;
   using acc = typename TR::acc_t;
   constexpr int VEC = TR::VEC;
+  constexpr bool LG = NC * VEC == 32;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t r0 = I.row_off[part];
   const int64_t m = I.row_off[part + 1] - r0;
@@ -72,11 +76,16 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) xr[q][e] = k < I.nvec ? xs[k * VEC + e] : acc(0);
   }
-  double g[NC][VEC];
+  double g[LG ? 1 : NC][LG ? 1 : VEC];
 #pragma unroll
   for (int q = 0; q < NC; ++q)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) g[q][e] = 0.0;
+    for (int e = 0; e < VEC; ++e) {
+      if constexpr (LG)
+        lg[(q * VEC + e) * BT + threadIdx.x] = 0.0;
+      else
+        g[q][e] = 0.0;
+    }
   const T* Ab = reinterpret_cast<const T*>(I.A) + r0 * I.ld;
   for (int64_t rt = lo + (int64_t)wv * R; rt < hi; rt += (int64_t)BW * R) {
     V v[R][NC];
@@ -128,7 +137,10 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode) {
         acc t = acc(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) t += er[r] * vget(v[r][q], c);
-        g[q][c] += (double)t;
+        if constexpr (LG)
+          lg[(q * VEC + c) * BT + threadIdx.x] += (double)t;
+        else
+          g[q][c] += (double)t;
       }
   }
   double* gp = I.gpart + (((int64_t)part * I.items_per_part + chunk) * BW + wv) * I.ld;
@@ -137,23 +149,28 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode) {
     const int k = lane + 64 * q;
     if (k < I.nvec) {
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) gp[k * VEC + c] = g[q][c];
+      for (int c = 0; c < VEC; ++c) {
+        if constexpr (LG)
+          gp[k * VEC + c] = lg[(q * VEC + c) * BT + threadIdx.x];
+        else
+          gp[k * VEC + c] = g[q][c];
+      }
     }
   }
 }
 
 template <typename T>
-__device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, int mode) {
+__device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, int mode, double* lg) {
   switch (I.shape) {
-    case 0: stream_item<T, 1, 1>(I, part, chunk, mode); break;
-    case 1: stream_item<T, 1, 2>(I, part, chunk, mode); break;
-    case 2: stream_item<T, 1, 4>(I, part, chunk, mode); break;
-    case 3: stream_item<T, 2, 1>(I, part, chunk, mode); break;
-    case 4: stream_item<T, 2, 2>(I, part, chunk, mode); break;
-    case 5: stream_item<T, 2, 4>(I, part, chunk, mode); break;
-    case 6: stream_item<T, 4, 1>(I, part, chunk, mode); break;
-    case 7: stream_item<T, 4, 2>(I, part, chunk, mode); break;
-    default: stream_item<T, 8, 1>(I, part, chunk, mode); break;
+    case 0: stream_item<T, 1, 1>(I, part, chunk, mode, lg); break;
+    case 1: stream_item<T, 1, 2>(I, part, chunk, mode, lg); break;
+    case 2: stream_item<T, 1, 4>(I, part, chunk, mode, lg); break;
+    case 3: stream_item<T, 2, 1>(I, part, chunk, mode, lg); break;
+    case 4: stream_item<T, 2, 2>(I, part, chunk, mode, lg); break;
+    case 5: stream_item<T, 2, 4>(I, part, chunk, mode, lg); break;
+    case 6: stream_item<T, 4, 1>(I, part, chunk, mode, lg); break;
+    case 7: stream_item<T, 4, 2>(I, part, chunk, mode, lg); break;
+    default: stream_item<T, 8, 1>(I, part, chunk, mode, lg); break;
   }
 }
 
@@ -257,9 +274,13 @@ __device__ GlobalArgs global_args_of(const BatchInst& I) {
   return g;
 }
 
-__global__ __launch_bounds__(BT) void batch_kernel(BatchArgs ba) {
-  __shared__ double rs[NJ_MAX];
-  __shared__ double ys[NJ_MAX];
+// Two workgroups per CU: at most 256 registers per lane (VGPRs and AGPRs).
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(BatchArgs ba) {
+  // the solve phase's right-hand side and intermediate vector, and the widest
+  // stream shape's partial sums, use the same LDS (phases never overlap)
+  __shared__ double big[2 * NJ_MAX > 32 * BT ? 2 * NJ_MAX : 32 * BT];
+  double* rs = big;
+  double* ys = big + NJ_MAX;
   __shared__ double shd[BW * (PSECT + 2)];
   __shared__ TopkShared<BT> tks;
   __shared__ int item_sh;
@@ -280,9 +301,9 @@ __global__ __launch_bounds__(BT) void batch_kernel(BatchArgs ba) {
       const BatchInst& I = ba.inst[w.inst];
       if (mode == 0 && (o >= I.outer || k_inner >= I.inner_iters)) continue;
       if (I.dtype == BCA_F64)
-        stream_item_dispatch<double>(I, w.a, w.b, mode);
+        stream_item_dispatch<double>(I, w.a, w.b, mode, big);
       else
-        stream_item_dispatch<float>(I, w.a, w.b, mode);
+        stream_item_dispatch<float>(I, w.a, w.b, mode, big);
     }
     ++phase;
   };

@@ -60,6 +60,18 @@ __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f,
 template <>
 __device__ __forceinline__ uint4 vzero<uint4>() { return make_uint4(0u, 0u, 0u, 0u); }
 
+// Streaming 16-byte load that bypasses cache retention (A is read once per pass
+// and never reused within it).
+template <typename V>
+__device__ __forceinline__ V load_stream(const V* p) {
+  static_assert(sizeof(V) == 16, "16-byte vectors only");
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  V v;
+  __builtin_memcpy(&v, &t, 16);
+  return v;
+}
+
 // Sum over the 64 lanes of a wavefront (every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -19,14 +19,17 @@
 // thread.  Products are formed in the arithmetic type of the storage (FP64 for
 // FP64 A, FP32 for FP32 and BF16 A); every sum longer than one thread's chunk
 // (across lanes, waves and row tiles) is carried in FP64.
+#include <cstdlib>
+
 #include "bca_internal.h"
 #include "prox_impl.h"
 
 namespace bca {
 
-// LACC: keep the FP64 partial sums of A^T e in LDS instead of registers (for
-// 8-element BF16 chunks, whose register footprint would otherwise halve occupancy).
-template <typename T, int NT, int NC, int R, bool LACC>
+// XL: keep the thread's slice of x in LDS instead of registers (BF16 rows carry
+// 8 columns per 16-byte chunk, so x and the FP64 sums would otherwise take
+// 3 registers per streamed byte and cut the workgroups per CU).
+template <typename T, int NT, int NC, int R, bool XL, bool PF>
 __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
   using TR = Traits<T>;
   using V = typename TR::vec_t;
@@ -35,7 +38,7 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
   constexpr int NW = NT / 64;
   __shared__ double red[NW][R];
   __shared__ double e_sh[R];
-  __shared__ double gsh[LACC ? NC * VEC : 1][LACC ? NT : 1];
+  __shared__ acc xsh[XL ? NC * VEC : 1][XL ? NT : 1];
 
   const int part = blockIdx.x / a.Gp;
   const int wg = blockIdx.x - part * a.Gp;
@@ -44,38 +47,56 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
   const acc* xs = reinterpret_cast<const acc*>(a.xs) + (int64_t)part * a.ld;
-  acc xr[NC][VEC];
+  acc xr[XL ? 1 : NC][XL ? 1 : VEC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const int k = tid + q * NT;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) xr[q][e] = (k < a.nvec) ? xs[k * VEC + e] : acc(0);
+    for (int e = 0; e < VEC; ++e) {
+      const acc xv = (k < a.nvec) ? xs[k * VEC + e] : acc(0);
+      if constexpr (XL)
+        xsh[q * VEC + e][tid] = xv;  // each thread reads back only its own slots
+      else
+        xr[q][e] = xv;
+    }
   }
-  double g[LACC ? 1 : NC][LACC ? 1 : VEC];
-  if constexpr (LACC) {
+  double g[NC][VEC];
 #pragma unroll
-    for (int q = 0; q < NC * VEC; ++q) gsh[q][tid] = 0.0;
-  } else {
+  for (int q = 0; q < NC; ++q)
 #pragma unroll
-    for (int q = 0; q < NC; ++q)
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) g[q][e] = 0.0;
-  }
+    for (int e = 0; e < VEC; ++e) g[q][e] = 0.0;
 
   const T* Ab = reinterpret_cast<const T*>(a.A) + r0 * a.ld;
   const int64_t ntiles = (m + R - 1) / R;
-  for (int64_t tile = wg; tile < ntiles; tile += a.Gp) {
-    const int64_t rt = tile * R;
-    V v[R][NC];
+  // Loads never branch: a row past the partition's end re-reads its last row and
+  // a chunk past the row's end re-reads its last chunk.  Neither changes a
+  // result: x is zero on the padded chunks (no dot contribution, no partial sum
+  // written out) and e is zero on the padded rows (no A^T e contribution).
+  int kc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) kc[q] = min(tid + q * NT, a.nvec - 1);
+  auto load_tile = [&](V (&dst)[R][NC], int64_t t) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int64_t row = rt + r;
+      const int64_t row = min(t * R + r, m - 1);
       const V* rp = reinterpret_cast<const V*>(Ab + row * a.ld);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int k = tid + q * NT;
-        v[r][q] = (row < m && k < a.nvec) ? rp[k] : vzero<V>();
-      }
+      for (int q = 0; q < NC; ++q) dst[r][q] = load_stream(rp + kc[q]);
+    }
+  };
+  V v[R][NC];
+  if constexpr (PF) {
+    if (wg < ntiles) load_tile(v, wg);
+  }
+  for (int64_t tile = wg; tile < ntiles; tile += a.Gp) {
+    const int64_t rt = tile * R;
+    // PF: the next tile's loads are issued before this tile's arithmetic and
+    // barriers, so HBM stays busy while the workgroup computes
+    V vn[PF ? R : 1][PF ? NC : 1];
+    if constexpr (PF) {
+      if (tile + a.Gp < ntiles) load_tile(vn, tile + a.Gp);
+    } else {
+      load_tile(v, tile);
     }
     // 1. partial dots of each row with x
     double dd[R];
@@ -85,7 +106,12 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
 #pragma unroll
       for (int q = 0; q < NC; ++q)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) d += vget(v[r][q], e) * xr[q][e];
+        for (int e = 0; e < VEC; ++e) {
+          if constexpr (XL)
+            d += vget(v[r][q], e) * xsh[q * VEC + e][tid];
+          else
+            d += vget(v[r][q], e) * xr[q][e];
+        }
       dd[r] = wave_sum((double)d);
     }
     if (lane == 0) {
@@ -120,6 +146,16 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
     }
     __syncthreads();
     // 5. accumulate e_k A_k (R products in the arithmetic type, then FP64)
+    if constexpr (VEC == 8) {
+      // BF16: widen the tile again here rather than keeping the 8 R NC widened
+      // values of step 1 alive across the barriers (the empty asm hides the
+      // raw words' values from the compiler, so the earlier widening is dead)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+          asm volatile("" : "+v"(v[r][q].x), "+v"(v[r][q].y), "+v"(v[r][q].z), "+v"(v[r][q].w));
+    }
     acc er[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) er[r] = (acc)e_sh[r];
@@ -130,11 +166,14 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
         acc t = acc(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) t += er[r] * vget(v[r][q], e);
-        if constexpr (LACC)
-          gsh[q * VEC + e][tid] += (double)t;
-        else
-          g[q][e] += (double)t;
+        g[q][e] += (double)t;
       }
+    if constexpr (PF) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) v[r][q] = vn[r][q];
+    }
   }
   double* gp = a.gpart + ((int64_t)part * a.Gp + wg) * a.ld;
 #pragma unroll
@@ -142,12 +181,7 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
     const int k = tid + q * NT;
     if (k < a.nvec) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        if constexpr (LACC)
-          gp[k * VEC + e] = gsh[q * VEC + e][tid];
-        else
-          gp[k * VEC + e] = g[q][e];
-      }
+      for (int e = 0; e < VEC; ++e) gp[k * VEC + e] = g[q][e];
     }
   }
 }
@@ -205,66 +239,106 @@ __global__ __launch_bounds__(NT) void objective_kernel(ObjArgs a) {
   if (tid == 0) a.partial[blockIdx.x] = lsum;
 }
 
-#define BCA_STREAM_NC_CASES(T, NT, RT)                                                           \
-  switch (nc) {                                                                                   \
-    case 1: hipLaunchKernelGGL((stream_kernel<T, NT, 1, RT, use_lacc<T, NT, 1>()>), grid, dim3(NT), 0, s, a); break;    \
-    case 2: hipLaunchKernelGGL((stream_kernel<T, NT, 2, RT, use_lacc<T, NT, 2>()>), grid, dim3(NT), 0, s, a); break;    \
-    case 3: hipLaunchKernelGGL((stream_kernel<T, NT, 3, RT, use_lacc<T, NT, 3>()>), grid, dim3(NT), 0, s, a); break;    \
-    case 4: hipLaunchKernelGGL((stream_kernel<T, NT, 4, RT, use_lacc<T, NT, 4>()>), grid, dim3(NT), 0, s, a); break;    \
-    case 5: hipLaunchKernelGGL((stream_kernel<T, NT, 5, RT, use_lacc<T, NT, 5>()>), grid, dim3(NT), 0, s, a); break;    \
-    case 6: hipLaunchKernelGGL((stream_kernel<T, NT, 6, RT, use_lacc<T, NT, 6>()>), grid, dim3(NT), 0, s, a); break;    \
-    default: hipLaunchKernelGGL((stream_kernel<T, NT, 8, RT, use_lacc<T, NT, 8>()>), grid, dim3(NT), 0, s, a); break;   \
-  }
+// Launch shape of the streaming pass for rows of nvec 16-byte chunks: threads per
+// workgroup, chunks per thread and rows per tile.  Up to `maxc` chunks per
+// thread with 256 threads, then 512 threads (still up to 256 VGPRs per lane),
+// then 1024.  FP32/FP64 rows: maxc 6, 4 rows per tile.  BF16 rows (8 columns
+// per chunk, so x and the FP64 sums take more registers per streamed byte, and
+// the next tile is prefetched): maxc 4, 4 rows per tile, or 2 rows per tile when
+// the environment variable BCA_BF16_STREAM_ROWS is 2 (measured at 16 x 100,000 x
+// 10,000: 5.66 TB/s with 4 rows, 4.97 TB/s with 2).
+struct StreamShape {
+  int nt, nc, r;
+};
 
-// Threads per workgroup and 16-byte chunks per thread for a row of nvec chunks:
-// up to 6 chunks per thread with 256 threads, then 512 threads (still up to 256
-// VGPRs per lane), then 1024.
-static void stream_shape(int nvec, int* nt, int* nc) {
-  if (nvec <= 6 * 256) {
-    *nt = 256;
-  } else if (nvec <= 6 * 512) {
-    *nt = 512;
-  } else {
-    *nt = 1024;
-  }
-  int c = (nvec + *nt - 1) / *nt;
-  if (c == 7) c = 8;
-  *nc = c < 1 ? 1 : c;
+static int bf16_rows() {
+  static int rows = [] {
+    const char* e = getenv("BCA_BF16_STREAM_ROWS");
+    return (e && atoi(e) == 2) ? 2 : 4;
+  }();
+  return rows;
 }
 
-// Rows per tile and where the FP64 partial sums live (LDS for BF16 when they fit
-// in 96 KB, so that a CU still holds more than one workgroup).
 template <typename T>
-struct StreamRows {
-  static constexpr int R = 4;
-  static constexpr bool LACC = false;
-};
-template <>
-struct StreamRows<bf16_t> {
-  static constexpr int R = 2;
-  static constexpr bool LACC = true;
-};
+static StreamShape stream_shape(int nvec) {
+  StreamShape sh;
+  sh.r = Traits<T>::VEC == 8 ? bf16_rows() : 4;
+  const int maxc = Traits<T>::VEC == 8 ? 4 : 6;
+  if (nvec <= maxc * 256) {
+    sh.nt = 256;
+  } else if (nvec <= maxc * 512) {
+    sh.nt = 512;
+  } else {
+    sh.nt = 1024;
+  }
+  int c = (nvec + sh.nt - 1) / sh.nt;
+  if (c == 7) c = 8;
+  sh.nc = c < 1 ? 1 : c;
+  return sh;
+}
+
+template <typename T>
+constexpr bool use_pf() {
+  return Traits<T>::VEC == 8;
+}
 
 template <typename T, int NT, int NC>
-constexpr bool use_lacc() {
-  return StreamRows<T>::LACC && NC * Traits<T>::VEC * NT * 8 <= 96 * 1024;
+constexpr bool use_xl() {
+  return Traits<T>::VEC == 8 && NC * Traits<T>::VEC * NT * 4 <= 128 * 1024;
 }
+
+// Calls F::template run<NT, NC, R>() for the shape (R in {2, 4}, 2 for BF16 only).
+template <typename T, typename F>
+static auto with_shape(const StreamShape& sh, F f) {
+#define BCA_NC(NT_, R_)                                  \
+  switch (sh.nc) {                                       \
+    case 1: return f.template run<NT_, 1, R_>();         \
+    case 2: return f.template run<NT_, 2, R_>();         \
+    case 3: return f.template run<NT_, 3, R_>();         \
+    case 4: return f.template run<NT_, 4, R_>();         \
+    case 5: return f.template run<NT_, 5, R_>();         \
+    case 6: return f.template run<NT_, 6, R_>();         \
+    default: return f.template run<NT_, 8, R_>();        \
+  }
+  if constexpr (Traits<T>::VEC == 8) {
+    if (sh.r == 2) {
+      if (sh.nt == 256) BCA_NC(256, 2)
+      if (sh.nt == 512) BCA_NC(512, 2)
+      BCA_NC(1024, 2)
+    }
+  }
+  if (sh.nt == 256) BCA_NC(256, 4)
+  if (sh.nt == 512) BCA_NC(512, 4)
+  BCA_NC(1024, 4)
+#undef BCA_NC
+}
+
+template <typename T>
+struct StreamLaunch {
+  const StreamArgs& a;
+  hipStream_t s;
+  template <int NT, int NC, int R>
+  hipError_t run() const {
+    hipLaunchKernelGGL((stream_kernel<T, NT, NC, R, use_xl<T, NT, NC>(), use_pf<T>()>), dim3(a.N * a.Gp), dim3(NT), 0,
+                       s, a);
+    return hipGetLastError();
+  }
+};
+
+template <typename T>
+struct StreamOcc {
+  template <int NT, int NC, int R>
+  int run() const {
+    int blocks = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, stream_kernel<T, NT, NC, R, use_xl<T, NT, NC>(), use_pf<T>()>, NT, 0);
+    return (e != hipSuccess || blocks < 1) ? 1 : blocks;
+  }
+};
 
 template <typename T>
 static hipError_t stream_dispatch(const StreamArgs& a, hipStream_t s) {
-  constexpr int RT = StreamRows<T>::R;
-  int nt, nc;
-  stream_shape(a.nvec, &nt, &nc);
-  if (nc > 8) return hipErrorInvalidValue;
-  dim3 grid(a.N * a.Gp);
-  if (nt == 256) {
-    BCA_STREAM_NC_CASES(T, 256, RT)
-  } else if (nt == 512) {
-    BCA_STREAM_NC_CASES(T, 512, RT)
-  } else {
-    BCA_STREAM_NC_CASES(T, 1024, RT)
-  }
-  return hipGetLastError();
+  return with_shape<T>(stream_shape<T>(a.nvec), StreamLaunch<T>{a, s});
 }
 
 hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s) {
@@ -276,34 +350,9 @@ hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s) {
   }
 }
 
-template <typename T, int NT>
-static int occ_nt(int nc) {
-  constexpr int RT = StreamRows<T>::R;
-  int blocks = 0;
-  hipError_t e = hipSuccess;
-#define BCA_OCC(NC_) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, stream_kernel<T, NT, NC_, RT, use_lacc<T, NT, NC_>()>, NT, 0)
-  switch (nc) {
-    case 1: BCA_OCC(1); break;
-    case 2: BCA_OCC(2); break;
-    case 3: BCA_OCC(3); break;
-    case 4: BCA_OCC(4); break;
-    case 5: BCA_OCC(5); break;
-    case 6: BCA_OCC(6); break;
-    default: BCA_OCC(8); break;
-  }
-#undef BCA_OCC
-  if (e != hipSuccess || blocks < 1) blocks = 1;
-  return blocks;
-}
-
 template <typename T>
 static int occ_one(int nvec) {
-  int nt, nc;
-  stream_shape(nvec, &nt, &nc);
-  if (nt == 256) return occ_nt<T, 256>(nc);
-  if (nt == 512) return occ_nt<T, 512>(nc);
-  return occ_nt<T, 1024>(nc);
+  return with_shape<T>(stream_shape<T>(nvec), StreamOcc<T>{});
 }
 
 int stream_occupancy_workgroups(int dtype, int nvec, int C) {
@@ -317,8 +366,8 @@ int stream_occupancy_workgroups(int dtype, int nvec, int C) {
 
 template <typename T>
 static hipError_t objective_dispatch(const ObjArgs& a, hipStream_t s) {
-  int nt, nc;
-  stream_shape(a.nvec, &nt, &nc);
+  const StreamShape sh = stream_shape<T>(a.nvec);
+  const int nt = sh.nt, nc = sh.nc;
   dim3 grid(a.N * a.Gp);
 #define BCA_OBJ(NT_, NC_) hipLaunchKernelGGL((objective_kernel<T, NT_, NC_>), grid, dim3(NT_), 0, s, a)
   if (nt == 256) {

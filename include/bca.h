@@ -208,7 +208,8 @@ int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream);
 
 /* Tile-shape autotuner of the batched streaming pass: groups the problems by
  * (storage type, row length, rows per partition), times every candidate shape
- * (rows per wavefront tile 1/2/4 x rows per work item 128/512/2048) on each group
+ * (rows per wavefront tile 1/2/4 x rows per work item 64/256/1024; a work item is
+ * one wavefront's chunk of rows) on each group
  * with a state-preserving streaming pass, and keeps the fastest per group.  The
  * ADMM state is not modified. */
 int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream);

@@ -5,23 +5,26 @@
 // one-problem path (Algorithm 2's K_in inner iterations, then the global step
 // of Algorithm 1), but here each phase is a list of independent work items
 // spanning all problems:
-//   SOLVE   item (problem, partition, block): the FP64 reduction of that block's
-//           A^T e partial sums into the right-hand side, then the two triangular
-//           products with the cached inverse factor (x_ij-step);
-//   STREAM  item (problem, partition, row chunk): the fused A-streaming pass over
-//           a chunk of rows, one wavefront per row tile (block predictions,
-//           sample-space average, omega-bar prox, nu update, e, partial A^T e);
+//   RHS     item (problem, partition, block): the FP64 reduction of that block's
+//           A^T e partial sums into the right-hand side of the x_ij-step;
+//   TRMV0/1 item (problem, partition, block, row range): the two triangular
+//           products with the cached inverse factor, y = W r then x += W^T y,
+//           each a phase of its own so a large block is shared by many workgroups;
+//   STREAM  item (problem, partition, row chunk): the fused streaming pass over
+//           a chunk of rows by one wavefront (block predictions, sample-space
+//           average, omega-bar prox, nu update, e, partial A^T e of the chunk);
 //   GLOBAL  item (problem): consensus average, exact (z,t) step, top-kappa
 //           s-step, v and u updates, residuals.
-// The workgroups of the persistent grid claim items of the current phase with an
-// atomic counter (largest items first) and meet at a grid barrier between
-// phases.  A problem's results depend only on its own items (fixed reduction
+// The workgroups (wavefronts, for stream items) of the persistent grid claim
+// items of the current phase with an atomic counter (largest items first) and
+// meet at a grid barrier between phases.  A problem's results depend only on its own items (fixed reduction
 // orders inside each item, tile shape chosen per problem shape, never per
 // batch), so a problem computes the same bits alone and inside any batch.
 //
 // Stream tile shapes: chunks per lane NC (a row of nvec 16-byte chunks is read by
-// one wavefront, NC = ceil(nvec / 64) rounded up to 1, 2, 4 or 8) and rows per
-// wave tile R in {1, 2, 4} with R NC <= 8, which bounds the kernel's register
+// one wavefront, NC = ceil(nvec / 64) rounded up to 1, 2, 4 or 8, or by a
+// segment of 16 or 32 lanes for rows of at most 16 or 32 chunks) and rows per
+// segment tile R in {1, 2, 4} with R NC <= 8, which bounds the kernel's register
 // footprint; rows per item is a runtime parameter.
 // The shape of each problem is picked by the autotuner in bca_api.hip.
 #include <hip/hip_cooperative_groups.h>
@@ -38,9 +41,14 @@ constexpr int BT = 256;
 constexpr int BW = BT / 64;
 constexpr int NJ_MAX = 1024;  // largest block width of a batched problem
 
-constexpr int kShapes = 9;
-static const int kShapeNC[kShapes] = {1, 1, 1, 2, 2, 2, 4, 4, 8};
-static const int kShapeR[kShapes] = {1, 2, 4, 1, 2, 4, 1, 2, 1};
+// Shapes (chunks per lane NC, rows per segment tile R, segments per wave S): a
+// wavefront is split into S segments of 64 / S lanes, each streaming its own rows,
+// so that rows of at most 16 or 32 chunks (short feature vectors) still keep
+// every lane busy; S follows from the row length, R is tuned.
+constexpr int kShapes = 15;
+static const int kShapeNC[kShapes] = {1, 1, 1, 2, 2, 2, 4, 4, 8, 1, 1, 1, 1, 1, 1};
+static const int kShapeR[kShapes] = {1, 2, 4, 1, 2, 4, 1, 2, 1, 1, 2, 4, 1, 2, 4};
+static const int kShapeS[kShapes] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 4, 4, 4};
 
 int batch_max_nvec() { return 64 * 8; }
 
@@ -48,22 +56,25 @@ int batch_shape_code(int nvec, int R) {
   int nc = 1;
   while (nc < 8 && 64 * nc < nvec) nc *= 2;
   if (64 * nc < nvec) return -1;
+  const int S = nc > 1 ? 1 : (nvec <= 16 ? 4 : (nvec <= 32 ? 2 : 1));
   for (int c = 0; c < kShapes; ++c)
-    if (kShapeNC[c] == nc && kShapeR[c] == R) return c;
+    if (kShapeNC[c] == nc && kShapeR[c] == R && kShapeS[c] == S) return c;
   return -1;
 }
 
 // LG: the widest FP32 shape (32 columns per lane) keeps its FP64 partial sums of
 // A^T e in LDS (lg, 32 x BT doubles) instead of 64 registers, which would
 // otherwise set the register budget of the whole persistent kernel.
-template <typename T, int NC, int R>
-__device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, double* lg) {
+template <typename T, int NC, int R, int S>
+__device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk, int mode, double* lg) {
   using TR = Traits<T>;
   using V = typename TR::vec_t;
   using acc = typename TR::acc_t;
   constexpr int VEC = TR::VEC;
   constexpr bool LG = NC * VEC == 32;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int LSEG = 64 / S;  // lanes per segment
+  const int lane = threadIdx.x & 63;
+  const int sl = lane % LSEG, seg = lane / LSEG;
   const int64_t r0 = I.row_off[part];
   const int64_t m = I.row_off[part + 1] - r0;
   const int64_t lo = (int64_t)chunk * I.rows_per_item;
@@ -72,7 +83,7 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, d
   acc xr[NC][VEC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    const int k = lane + 64 * q;
+    const int k = sl + LSEG * q;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) xr[q][e] = k < I.nvec ? xs[k * VEC + e] : acc(0);
   }
@@ -87,17 +98,53 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, d
         g[q][e] = 0.0;
     }
   const T* Ab = reinterpret_cast<const T*>(I.A) + r0 * I.ld;
-  for (int64_t rt = lo + (int64_t)wv * R; rt < hi; rt += (int64_t)BW * R) {
-    V v[R][NC];
+  // Branch-free loads (rows past the item's end re-read its last row, chunks past
+  // the row's end its last chunk: x is zero there and e is zero on such rows), and
+  // the wave's next tile is loaded before the current one is processed.
+  int kc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) kc[q] = min(sl + LSEG * q, I.nvec - 1);
+  // a wave tile is S R rows: segment s takes rows rt + s R .. rt + s R + R - 1
+  auto load_tile = [&](V (&dst)[R][NC], int64_t t0) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int64_t row = rt + r;
+      const int64_t row = min(t0 + seg * R + r, hi - 1);
       const V* rp = reinterpret_cast<const V*>(Ab + row * I.ld);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int k = lane + 64 * q;
-        v[r][q] = (row < hi && k < I.nvec) ? rp[k] : vzero<V>();
-      }
+      for (int q = 0; q < NC; ++q) dst[r][q] = load_stream(rp + kc[q]);
+    }
+  };
+  // Per-row values (b, omega-bar, nu) of a tile are loaded together with its A
+  // rows: loads complete in issue order, so a row value loaded after the next
+  // tile's prefetch would make the wavefront wait for that whole prefetch.
+  struct RowVals {
+    double b, om, nu;
+  };
+  auto load_rows = [&](int64_t t0) {
+    RowVals rv{0.0, 0.0, 0.0};
+    if (sl < R) {
+      const int64_t gr = r0 + min(t0 + seg * R + sl, hi - 1);
+      rv.b = I.b[gr];
+      rv.om = I.omega[gr];
+      rv.nu = I.nu[gr];
+    }
+    return rv;
+  };
+  constexpr int64_t STEP = (int64_t)S * R;
+  V v[R][NC];
+  RowVals rv{0.0, 0.0, 0.0};
+  if (lo < hi) {
+    load_tile(v, lo);
+    rv = load_rows(lo);
+  }
+  for (int64_t rt = lo; rt < hi; rt += STEP) {
+    // the next tile's loads go out before this tile's arithmetic; its rows lie
+    // beyond this tile's, so reading their omega-bar and nu here is safe
+    V vn[R][NC];
+    RowVals rvn{0.0, 0.0, 0.0};
+    if (rt + STEP < hi) {
+      load_tile(vn, rt + STEP);
+      rvn = load_rows(rt + STEP);
     }
     double mine = 0.0;
 #pragma unroll
@@ -107,29 +154,31 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, d
       for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) d += vget(v[r][q], e) * xr[q][e];
-      const double s = wave_sum((double)d);
-      if (lane == r) mine = s;
+      double sv = (double)d;
+#pragma unroll
+      for (int o = LSEG / 2; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
+      if (sl == r) mine = sv;
     }
     double e = 0.0;
-    const int64_t row = rt + lane;
-    if (lane < R && row < hi) {
+    const int64_t row = rt + seg * R + sl;
+    if (sl < R && row < hi) {
       const int64_t gr = r0 + row;
       const double av = mine * I.inv_M;
-      double nu = I.nu[gr];
+      double nu = rv.nu;
       if (mode == 0) {
-        const double om = prox_scalar(I.loss, av + nu, I.b[gr], I.M, I.rho_l,
-                                      I.loss == BCA_LOSS_SQUARED ? 0.0 : I.omega[gr]);
+        const double om = prox_scalar(I.loss, av + nu, rv.b, I.M, I.rho_l,
+                                      I.loss == BCA_LOSS_SQUARED ? 0.0 : rv.om);
         nu = nu + av - om;
         I.omega[gr] = om;
         I.nu[gr] = nu;
         e = om - av - nu;
       } else {
-        e = I.omega[gr] - av - nu;
+        e = rv.om - av - nu;
       }
     }
     acc er[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) er[r] = (acc)__shfl(e, r, 64);
+    for (int r = 0; r < R; ++r) er[r] = (acc)__shfl(e, seg * LSEG + r, 64);
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
@@ -142,18 +191,34 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, d
         else
           g[q][c] += (double)t;
       }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) v[r][q] = vn[r][q];
+    rv = rvn;
   }
-  double* gp = I.gpart + (((int64_t)part * I.items_per_part + chunk) * BW + wv) * I.ld;
+  // segments hold sums over different rows for the same columns: combine them
+  if constexpr (S > 1 && !LG) {
 #pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const int k = lane + 64 * q;
-    if (k < I.nvec) {
+    for (int q = 0; q < NC; ++q)
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) {
-        if constexpr (LG)
-          gp[k * VEC + c] = lg[(q * VEC + c) * BT + threadIdx.x];
-        else
-          gp[k * VEC + c] = g[q][c];
+      for (int c = 0; c < VEC; ++c)
+#pragma unroll
+        for (int o = LSEG; o < 64; o <<= 1) g[q][c] += __shfl_xor(g[q][c], o, 64);
+  }
+  double* gp = I.gpart + ((int64_t)part * I.items_per_part + chunk) * I.ld;
+  if (seg == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int k = sl + LSEG * q;
+      if (k < I.nvec) {
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+          if constexpr (LG)
+            gp[k * VEC + c] = lg[(q * VEC + c) * BT + threadIdx.x];
+          else
+            gp[k * VEC + c] = g[q][c];
+        }
       }
     }
   }
@@ -162,27 +227,35 @@ __device__ void stream_item(const BatchInst& I, int part, int chunk, int mode, d
 template <typename T>
 __device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, int mode, double* lg) {
   switch (I.shape) {
-    case 0: stream_item<T, 1, 1>(I, part, chunk, mode, lg); break;
-    case 1: stream_item<T, 1, 2>(I, part, chunk, mode, lg); break;
-    case 2: stream_item<T, 1, 4>(I, part, chunk, mode, lg); break;
-    case 3: stream_item<T, 2, 1>(I, part, chunk, mode, lg); break;
-    case 4: stream_item<T, 2, 2>(I, part, chunk, mode, lg); break;
-    case 5: stream_item<T, 2, 4>(I, part, chunk, mode, lg); break;
-    case 6: stream_item<T, 4, 1>(I, part, chunk, mode, lg); break;
-    case 7: stream_item<T, 4, 2>(I, part, chunk, mode, lg); break;
-    default: stream_item<T, 8, 1>(I, part, chunk, mode, lg); break;
+    case 0: stream_item<T, 1, 1, 1>(I, part, chunk, mode, lg); break;
+    case 1: stream_item<T, 1, 2, 1>(I, part, chunk, mode, lg); break;
+    case 2: stream_item<T, 1, 4, 1>(I, part, chunk, mode, lg); break;
+    case 3: stream_item<T, 2, 1, 1>(I, part, chunk, mode, lg); break;
+    case 4: stream_item<T, 2, 2, 1>(I, part, chunk, mode, lg); break;
+    case 5: stream_item<T, 2, 4, 1>(I, part, chunk, mode, lg); break;
+    case 6: stream_item<T, 4, 1, 1>(I, part, chunk, mode, lg); break;
+    case 7: stream_item<T, 4, 2, 1>(I, part, chunk, mode, lg); break;
+    case 8: stream_item<T, 8, 1, 1>(I, part, chunk, mode, lg); break;
+    case 9: stream_item<T, 1, 1, 2>(I, part, chunk, mode, lg); break;
+    case 10: stream_item<T, 1, 2, 2>(I, part, chunk, mode, lg); break;
+    case 11: stream_item<T, 1, 4, 2>(I, part, chunk, mode, lg); break;
+    case 12: stream_item<T, 1, 1, 4>(I, part, chunk, mode, lg); break;
+    case 13: stream_item<T, 1, 2, 4>(I, part, chunk, mode, lg); break;
+    default: stream_item<T, 1, 4, 4>(I, part, chunk, mode, lg); break;
   }
 }
 
-// x_ij-step of one block: rhs = rho_l sum_w gpart_w + rho_c (z - u) - shift x,
-// y = W rhs, x += W^T y (W = L^-1, packed rows / packed columns).
-__device__ __noinline__ void solve_item(const BatchInst& I, int part, int blk, double* rs, double* ys) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// x_ij-step of one block, in three phases of independent items so that a large
+// block's factor is read by many workgroups at once:
+//   RHS   (partition, block): r = rho_l sum_w gpart_w + rho_c (z - u) - shift x;
+//   TRMV0 (partition, block, row range): y_r = sum_{c <= r} W[r][c] r_c   (packed rows);
+//   TRMV1 (partition, block, row range): x_r += sum_{c >= r} W[c][r] y_c  (packed columns).
+__device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk) {
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
-  const int P = I.items_per_part * BW;
+  const int P = I.items_per_part;
   const double* gb = I.gpart + (int64_t)part * P * I.ld;
-  for (int c = tid; c < nj; c += BT) {
+  for (int c = threadIdx.x; c < nj; c += BT) {
     const int k = c0 + c;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int w = 0;
@@ -194,56 +267,96 @@ __device__ __noinline__ void solve_item(const BatchInst& I, int part, int blk, d
     }
     for (; w < P; ++w) s0 += gb[(int64_t)w * I.ld + k];
     const int64_t o = (int64_t)part * I.n + k;
-    rs[c] = I.rho_l * ((s0 + s1) + (s2 + s3)) + I.rho_c * (I.z[k] - I.u[o]) - I.shift * I.x[o];
+    I.rhs[o] = I.rho_l * ((s0 + s1) + (s2 + s3)) + I.rho_c * (I.z[k] - I.u[o]) - I.shift * I.x[o];
   }
+}
+
+// Rows [lo, hi) of one triangular product.  A wavefront takes 4 consecutive rows
+// at once (groups lo + 4 g, g = wave, wave + 4, ...) and walks them together in
+// chunks of 256 entries per row, so 16 loads per lane are in flight; each row's
+// sum has a fixed order (4 partial sums per lane, then the wavefront reduction).
+__device__ __noinline__ void trmv_item(const BatchInst& I, int part, int blk, int lo, int hi, int tr,
+                                       double* vsh) {
+  constexpr int G = 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c0 = I.col_off[blk];
+  const int nj = I.col_off[blk + 1] - c0;
+  const double* vin = (tr == 0 ? I.rhs : I.y) + (int64_t)part * I.n + c0;
+  for (int c = tid; c < nj; c += BT) vsh[c] = vin[c];
   __syncthreads();
-  const int64_t fo = I.fac_off[part * I.M + blk];
-  const int pairs = (nj + 1) / 2;
-  for (int tr = 0; tr < 2; ++tr) {
-    const double* F = (tr == 0 ? I.wr : I.wc) + fo;
-    const double* vin = tr == 0 ? rs : ys;
-    for (int pr = wv; pr < pairs; pr += BW) {
-      for (int h = 0; h < 2; ++h) {
-        const int r = h == 0 ? pr : nj - 1 - pr;
-        if (h == 1 && r == pr) break;
+  const double* F = (tr == 0 ? I.wr : I.wc) + I.fac_off[part * I.M + blk];
+  for (int r0 = lo + G * wv; r0 < hi; r0 += G * BW) {
+    const double* f[G];
+    const double* v[G];
+    int len[G];
+    int maxlen = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int r = r0 + g;
+      if (r < hi) {
         int64_t off;
-        int st, len;
+        int st;
         if (tr == 0) {
           off = (int64_t)r * (r + 1) / 2;
           st = 0;
-          len = r + 1;
+          len[g] = r + 1;
         } else {
           off = (int64_t)r * nj - (int64_t)r * (r - 1) / 2;
           st = r;
-          len = nj - r;
+          len[g] = nj - r;
         }
-        const double* f = F + off;
-        double s0 = 0.0, s1 = 0.0;
-        int e = lane;
-        for (; e + 64 < len; e += 128) {
-          s0 += f[e] * vin[st + e];
-          s1 += f[e + 64] * vin[st + e + 64];
+        f[g] = F + off;
+        v[g] = vsh + st;
+      } else {
+        f[g] = F;
+        v[g] = vsh;
+        len[g] = 0;
+      }
+      maxlen = max(maxlen, len[g]);
+    }
+    double s[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[g][u] = 0.0;
+    for (int e0 = 0; e0 < maxlen; e0 += 256) {
+      double fv[G][4];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + 64 * u + lane;
+          fv[g][u] = e < len[g] ? f[g][e] : 0.0;
         }
-        if (e < len) s0 += f[e] * vin[st + e];
-        const double tot = wave_sum(s0 + s1);
-        if (lane == 0) {
-          if (tr == 0) {
-            ys[r] = tot;
-          } else {
-            const int64_t o = (int64_t)part * I.n + c0 + r;
-            const double xn = I.x[o] + tot;
-            I.x[o] = xn;
-            const int64_t so = (int64_t)part * I.ld + c0 + r;
-            if (I.dtype == BCA_F64)
-              reinterpret_cast<double*>(I.xs)[so] = xn;
-            else
-              reinterpret_cast<float*>(I.xs)[so] = (float)xn;
-          }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + 64 * u + lane;
+          if (e < len[g]) s[g][u] += fv[g][u] * v[g][e];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const double tot = wave_sum((s[g][0] + s[g][1]) + (s[g][2] + s[g][3]));
+      const int r = r0 + g;
+      if (lane == 0 && r < hi) {
+        const int64_t o = (int64_t)part * I.n + c0 + r;
+        if (tr == 0) {
+          I.y[o] = tot;
+        } else {
+          const double xn = I.x[o] + tot;
+          I.x[o] = xn;
+          const int64_t so = (int64_t)part * I.ld + c0 + r;
+          if (I.dtype == BCA_F64)
+            reinterpret_cast<double*>(I.xs)[so] = xn;
+          else
+            reinterpret_cast<float*>(I.xs)[so] = (float)xn;
         }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();  // vsh is reused by the next item
 }
 
 // Out of line, with 7 multisection points per round, so that the global step's
@@ -278,9 +391,7 @@ __device__ GlobalArgs global_args_of(const BatchInst& I) {
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(BatchArgs ba) {
   // the solve phase's right-hand side and intermediate vector, and the widest
   // stream shape's partial sums, use the same LDS (phases never overlap)
-  __shared__ double big[2 * NJ_MAX > 32 * BT ? 2 * NJ_MAX : 32 * BT];
-  double* rs = big;
-  double* ys = big + NJ_MAX;
+  __shared__ double big[NJ_MAX > 32 * BT ? NJ_MAX : 32 * BT];
   __shared__ double shd[BW * (PSECT + 2)];
   __shared__ TopkShared<BT> tks;
   __shared__ int item_sh;
@@ -295,8 +406,15 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
     __syncthreads();
     return it;
   };
+  // stream items are claimed by single wavefronts (no workgroup barrier between
+  // items, so the 8 wavefronts of a CU overlap their per-item latencies)
+  auto claim_wave = [&]() {
+    int it = 0;
+    if ((threadIdx.x & 63) == 0) it = (int)atomicAdd(&ba.counters[phase], 1u);
+    return __shfl(it, 0, 64);
+  };
   auto run_stream = [&](const BatchItem* items, int count, int mode, int k_inner, int o) {
-    for (int it = claim(); it < count; it = claim()) {
+    for (int it = claim_wave(); it < count; it = claim_wave()) {
       const BatchItem w = items[it];
       const BatchInst& I = ba.inst[w.inst];
       if (mode == 0 && (o >= I.outer || k_inner >= I.inner_iters)) continue;
@@ -315,14 +433,24 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
   }
   for (int o = 0; o < ba.outer; ++o) {
     for (int k = 0; k < ba.inner_max; ++k) {
-      for (int it = claim(); it < ba.n_solve; it = claim()) {
-        const BatchItem w = ba.solve_items[it];
+      for (int it = claim(); it < ba.n_rhs; it = claim()) {
+        const BatchItem w = ba.rhs_items[it];
         const BatchInst& I = ba.inst[w.inst];
         if (o >= I.outer || k >= I.inner_iters) continue;
-        solve_item(I, w.a, w.b, rs, ys);
+        rhs_item(I, w.a, w.b);
       }
       ++phase;
       grid.sync();
+      for (int tr = 0; tr < 2; ++tr) {
+        for (int it = claim(); it < ba.n_trmv[tr]; it = claim()) {
+          const BatchItem w = ba.trmv_items[tr][it];
+          const BatchInst& I = ba.inst[w.inst];
+          if (o >= I.outer || k >= I.inner_iters) continue;
+          trmv_item(I, w.a, w.b, w.c, w.d, tr, big);
+        }
+        ++phase;
+        grid.sync();
+      }
       run_stream(ba.stream_items, ba.n_stream, 0, k, o);
       grid.sync();
     }

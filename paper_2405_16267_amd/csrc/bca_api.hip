@@ -129,6 +129,49 @@ void dfree(bca_problem P, void* p) {
 
 int xs_is_f64(bca_problem P) { return P->dtype == BCA_F64 ? 1 : 0; }
 
+// Host-to-device copy of a pitched block (m rows of `width` bytes, host pitch
+// spitch, device pitch dpitch).  A pitched copy straight from pageable host
+// memory moves row by row (about 0.5 GB/s measured); instead, row chunks are
+// copied contiguously (host padding included) into a device staging buffer and
+// placed with a device-to-device pitched copy.  One staging buffer per process
+// and device, guarded by a mutex held until the stream has drained.
+std::mutex g_stage_mu;
+void* g_stage[64] = {nullptr};
+constexpr size_t kStageBytes = 64u << 20;
+
+hipError_t copy_h2d_pitched(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                            int64_t m, hipStream_t s) {
+  if (spitch == width && dpitch == width)
+    return hipMemcpyAsync(dst, src, (size_t)m * width, hipMemcpyHostToDevice, s);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (!g_stage[dev]) {
+    e = hipMalloc(&g_stage[dev], kStageBytes);
+    if (e != hipSuccess) {
+      g_stage[dev] = nullptr;
+      return e;
+    }
+  }
+  char* st = reinterpret_cast<char*>(g_stage[dev]);
+  const int64_t rows_per = spitch <= kStageBytes ? (int64_t)(kStageBytes / spitch) : 0;
+  if (rows_per == 0) return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, m, hipMemcpyHostToDevice, s);
+  for (int64_t r = 0; r < m && e == hipSuccess; r += rows_per) {
+    const int64_t k = std::min<int64_t>(rows_per, m - r);
+    // the last row of a chunk only needs `width` bytes (the host block may end there)
+    const size_t bytes = (size_t)(k - 1) * spitch + width;
+    e = hipMemcpyAsync(st, reinterpret_cast<const char*>(src) + (size_t)r * spitch, bytes,
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(reinterpret_cast<char*>(dst) + (size_t)r * dpitch, dpitch, st, spitch, width, k,
+                           hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the staging buffer is free again
+  return e;
+}
+
 // Record a timing event pair around one launch when timing is on.
 struct Timer {
   bca_problem P;
@@ -443,7 +486,10 @@ int bca_set_data(bca_problem P, int32_t part, const void* A, int64_t ld, const v
   const int64_t m = P->rows[part];
   const hipMemcpyKind kind = mem == BCA_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   char* dstA = reinterpret_cast<char*>(P->A) + (size_t)P->row_off[part] * P->ld * es;
-  HIP_TRY(hipMemcpy2DAsync(dstA, P->ld * es, A, ld * es, P->n * es, m, kind, P->stream));
+  if (mem == BCA_MEM_HOST)
+    HIP_TRY(copy_h2d_pitched(dstA, P->ld * es, A, ld * es, P->n * es, m, P->stream));
+  else
+    HIP_TRY(hipMemcpy2DAsync(dstA, P->ld * es, A, ld * es, P->n * es, m, kind, P->stream));
   const bool softmax = P->p.loss == BCA_LOSS_SOFTMAX;
   if (softmax)
     HIP_TRY(hipMemcpyAsync(P->y + P->row_off[part], b, m * sizeof(int32_t), kind, P->stream));
@@ -871,7 +917,7 @@ int batch_rows_tile(bca_problem P) {
   if (P->b_rows_tile > 0) return P->b_rows_tile;
   return batch_shape_code(P->nvec, 2) >= 0 ? 2 : 1;
 }
-int batch_rows_item(bca_problem P) { return P->b_rows_item > 0 ? P->b_rows_item : 512; }
+int batch_rows_item(bca_problem P) { return P->b_rows_item > 0 ? P->b_rows_item : 256; }
 
 int batch_check(bca_problem P) {
   if (!P) return fail(BCA_E_INVALID, "null problem in batch");
@@ -901,7 +947,7 @@ int64_t batch_items_per_part(bca_problem P) {
 }
 
 int batch_ensure_partials(bca_problem P) {
-  const size_t need = (size_t)P->N * batch_items_per_part(P) * 4 * P->ld;
+  const size_t need = (size_t)P->N * batch_items_per_part(P) * P->ld;
   if (P->bgpart && P->bgpart_count >= need) return BCA_OK;
   if (P->bgpart) dfree(P, P->bgpart);
   P->bgpart = nullptr;
@@ -930,6 +976,8 @@ BatchInst batch_desc(bca_problem P, int outer) {
   I.work = P->work;
   I.status = P->status;
   I.gpart = P->bgpart;
+  I.rhs = P->rhs;
+  I.y = P->tmp;
   I.wr = P->wr;
   I.wc = P->wc;
   I.fac_off = P->d_fac_off;
@@ -961,8 +1009,12 @@ BatchInst batch_desc(bca_problem P, int outer) {
 int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, hipStream_t s,
                  bool stream_only, float* ms) {
   std::vector<BatchInst> desc(count);
-  std::vector<BatchItem> solve, stream, primei;
+  std::vector<BatchItem> solve, stream, primei, trmv[2];
   int outer_max = 0, inner_max = 0;
+  // Row ranges of the triangular products: about kTrmvWork factor entries per
+  // item (row r of W has r + 1 entries, column r has n_j - r), fixed by n_j alone
+  // so a problem is split the same way in every batch.
+  constexpr int64_t kTrmvWork = 32768;
   for (int r = 0; r < count; ++r) {
     bca_problem P = probs[r];
     TRY(batch_ensure_partials(P));
@@ -971,19 +1023,55 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     inner_max = std::max(inner_max, P->p.inner_iters);
     const int ipp = desc[r].items_per_part;
     for (int i = 0; i < P->N; ++i) {
-      for (int j = 0; j < P->M; ++j) solve.push_back({r, i, j, 0});
+      for (int j = 0; j < P->M; ++j) {
+        solve.push_back({r, i, j, 0, 0});
+        const int nj = P->col_off[j + 1] - P->col_off[j];
+        for (int tr = 0; tr < 2; ++tr) {
+          int lo = 0;
+          int64_t acc = 0;
+          for (int row = 0; row < nj; ++row) {
+            acc += tr == 0 ? row + 1 : nj - row;
+            if (acc >= kTrmvWork || row == nj - 1) {
+              trmv[tr].push_back({r, i, j, lo, row + 1});
+              lo = row + 1;
+              acc = 0;
+            }
+          }
+        }
+      }
       for (int c = 0; c < ipp; ++c) {
-        stream.push_back({r, i, c, 0});
-        if (P->need_bprime || stream_only) primei.push_back({r, i, c, 0});
+        stream.push_back({r, i, c, 0, 0});
+        if (P->need_bprime || stream_only) primei.push_back({r, i, c, 0, 0});
       }
     }
   }
-  // largest work first: solve items by n_j^2, stream items by rows x vectors
+  // largest work first: rhs items by n_j x partials, triangular items by
+  // entries, stream items by rows x vectors
   auto solve_cost = [&](const BatchItem& w) {
     bca_problem P = probs[w.inst];
     const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
-    return nj * nj;
+    return nj * batch_items_per_part(P);
   };
+  auto trmv_cost = [&](int tr) {
+    return [&, tr](const BatchItem& w) {
+      bca_problem P = probs[w.inst];
+      const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
+      int64_t c = 0;
+      for (int64_t row = w.c; row < w.d; ++row) c += tr == 0 ? row + 1 : nj - row;
+      return c;
+    };
+  };
+  for (int tr = 0; tr < 2; ++tr) {
+    auto cost = trmv_cost(tr);
+    std::vector<std::pair<int64_t, BatchItem>> keyed;
+    keyed.reserve(trmv[tr].size());
+    for (const auto& w : trmv[tr]) keyed.push_back({cost(w), w});
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const std::pair<int64_t, BatchItem>& a, const std::pair<int64_t, BatchItem>& b) {
+                       return a.first > b.first;
+                     });
+    for (size_t q = 0; q < keyed.size(); ++q) trmv[tr][q] = keyed[q].second;
+  }
   auto stream_cost = [&](const BatchItem& w) {
     bca_problem P = probs[w.inst];
     const int64_t lo = (int64_t)w.b * batch_rows_item(P);
@@ -1000,11 +1088,13 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     return stream_cost(a) > stream_cost(b);
   });
   if (stream_only) outer_max = 0;
-  const int phases = (primei.empty() ? 0 : 1) + outer_max * (2 * inner_max + 1);
+  const int phases = (primei.empty() ? 0 : 1) + outer_max * (4 * inner_max + 1);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t off_desc = 0;
   const size_t off_solve = off_desc + al(desc.size() * sizeof(BatchInst));
-  const size_t off_stream = off_solve + al(solve.size() * sizeof(BatchItem));
+  const size_t off_t0 = off_solve + al(solve.size() * sizeof(BatchItem));
+  const size_t off_t1 = off_t0 + al(trmv[0].size() * sizeof(BatchItem));
+  const size_t off_stream = off_t1 + al(trmv[1].size() * sizeof(BatchItem));
   const size_t off_prime = off_stream + al(stream.size() * sizeof(BatchItem));
   const size_t off_cnt = off_prime + al(primei.size() * sizeof(BatchItem));
   const size_t total = off_cnt + al((size_t)std::max(phases, 1) * sizeof(unsigned int));
@@ -1019,6 +1109,10 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   HIP_TRY(hipMemcpyAsync(base + off_desc, desc.data(), desc.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s));
   if (!solve.empty())
     HIP_TRY(hipMemcpyAsync(base + off_solve, solve.data(), solve.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  if (!trmv[0].empty())
+    HIP_TRY(hipMemcpyAsync(base + off_t0, trmv[0].data(), trmv[0].size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  if (!trmv[1].empty())
+    HIP_TRY(hipMemcpyAsync(base + off_t1, trmv[1].data(), trmv[1].size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   if (!stream.empty())
     HIP_TRY(hipMemcpyAsync(base + off_stream, stream.data(), stream.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   if (!primei.empty())
@@ -1027,8 +1121,12 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   BatchArgs a{};
   a.inst = reinterpret_cast<const BatchInst*>(base + off_desc);
   a.count = count;
-  a.solve_items = reinterpret_cast<const BatchItem*>(base + off_solve);
-  a.n_solve = (int)solve.size();
+  a.rhs_items = reinterpret_cast<const BatchItem*>(base + off_solve);
+  a.n_rhs = (int)solve.size();
+  a.trmv_items[0] = reinterpret_cast<const BatchItem*>(base + off_t0);
+  a.trmv_items[1] = reinterpret_cast<const BatchItem*>(base + off_t1);
+  a.n_trmv[0] = (int)trmv[0].size();
+  a.n_trmv[1] = (int)trmv[1].size();
   a.stream_items = reinterpret_cast<const BatchItem*>(base + off_stream);
   a.n_stream = (int)stream.size();
   a.prime_items = reinterpret_cast<const BatchItem*>(base + off_prime);
@@ -1144,12 +1242,12 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
     buckets[b].push_back(P);
   }
   const int tiles[3] = {1, 2, 4};
-  const int items[3] = {128, 512, 2048};
+  const int items[3] = {64, 256, 1024};
   for (size_t b = 0; b < buckets.size(); ++b) {
     auto& bp = buckets[b];
     for (auto P : bp) TRY(batch_check_basic(P));
     float best = 1e30f;
-    int bt = 2, bi = 512;
+    int bt = 2, bi = 256;
     for (int ti = 0; ti < 3; ++ti) {
       if (batch_shape_code(bp[0]->nvec, tiles[ti]) < 0) continue;
       for (int ii = 0; ii < 3; ++ii) {

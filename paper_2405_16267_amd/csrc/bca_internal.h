@@ -216,6 +216,8 @@ struct BatchInst {
   double* work;
   int* status;
   double* gpart;           // N x (items_per_part * 4) x ld wave partials of A^T e
+  double* rhs;             // N x n right-hand sides of the x_ij-step
+  double* y;               // N x n intermediate W r of the x_ij-step
   const double* wr;
   const double* wc;
   const int64_t* fac_off;
@@ -227,14 +229,16 @@ struct BatchInst {
 };
 
 struct BatchItem {
-  int inst, a, b, c;
+  int inst, a, b, c, d;
 };
 
 struct BatchArgs {
   const BatchInst* inst;
   int count;
-  const BatchItem* solve_items;    // (inst, partition, block), largest first
-  int n_solve;
+  const BatchItem* rhs_items;      // (inst, partition, block), largest first
+  int n_rhs;
+  const BatchItem* trmv_items[2];  // (inst, partition, block, first row, end row): y = W r, x += W^T y
+  int n_trmv[2];
   const BatchItem* stream_items;   // (inst, partition, chunk), largest first
   int n_stream;
   const BatchItem* prime_items;    // stream items of problems whose partial sums are stale

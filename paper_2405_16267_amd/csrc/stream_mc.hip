@@ -4,8 +4,9 @@
 // step is a C-dimensional prox per sample and A_i^T E is n x C.  Thread t owns
 // the features t, t + NT, ..., and for each of them all C columns of X in
 // registers; the per-row dots (R rows x C classes) are reduced across the
-// workgroup, one thread per row runs the softmax prox, and e_k (C values) is
-// broadcast back for the A_i^T E accumulation.  Tile partial sums of A_i^T E are
+// workgroup, the first wavefront runs the softmax prox of the R rows (a 16-lane
+// group per row, a lane per class), and e_k (C values) is broadcast back for the
+// A_i^T E accumulation.  Tile partial sums of A_i^T E are
 // formed in the arithmetic type and folded every FLUSH tiles into the
 // workgroup's FP64 partial vector in global memory.
 //
@@ -39,74 +40,85 @@ __device__ double lse_c(const double* q, int C) {
   return mx + log(s);
 }
 
-// F(q) and, if p/g are given, softmax probabilities and gradient.
-__device__ double softmax_F(const double* q, const double* q0, int y, double beta, int C) {
-  double f = lse_c(q, C) - q[y];
-  double r = 0.0;
-  for (int c = 0; c < C; ++c) r += (q[c] - q0[c]) * (q[c] - q0[c]);
-  return f + 0.5 * beta * r;
+// The softmax prox runs with one 16-lane group of a wavefront per sample and one
+// lane per class (lane = 16 r + c): every sum, maximum and exponential over the
+// classes is a group operation, so a wavefront solves 4 samples at the cost of
+// one.  act: c < C; valid: the group's sample exists.
+__device__ __forceinline__ double gsum16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double gmax16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
 }
 
-__device__ double softmax_grad(const double* q, const double* q0, int y, double beta, int C,
-                               double* p, double* g) {
-  const double l = lse_c(q, C);
-  double gn = 0.0;
-  for (int c = 0; c < C; ++c) {
-    p[c] = exp(q[c] - l);
-    g[c] = p[c] - (c == y ? 1.0 : 0.0) + beta * (q[c] - q0[c]);
-    gn += g[c] * g[c];
-  }
-  return sqrt(gn);
+struct LseGrad {
+  double l, p, g, gn;
+};
+
+// log-sum-exp of the group's q, and this lane's probability and gradient entry
+__device__ __forceinline__ LseGrad lse_grad16(double q, double q0, bool act, bool is_y, double beta) {
+  LseGrad r;
+  const double mx = gmax16(act ? q : -INFINITY);
+  const double s = gsum16(act ? exp(q - mx) : 0.0);
+  r.l = mx + log(s);
+  r.p = act ? exp(q - r.l) : 0.0;
+  r.g = act ? r.p - (is_y ? 1.0 : 0.0) + beta * (q - q0) : 0.0;
+  r.gn = sqrt(gsum16(r.g * r.g));
+  return r;
 }
 
-// scratch: 6 * C doubles (q0, q, p, g, step, trial); c: C values; w_prev (the
-// previous omega-bar of the sample) seeds the iteration; result in w (C values)
-__device__ void prox_softmax_row(const double* cvec, const double* w_prev, int y, int M,
-                                 double rho_l, int C, double* scratch, double* w) {
-  double* q0 = scratch;
-  double* q = scratch + C;
-  double* p = scratch + 2 * C;
-  double* g = scratch + 3 * C;
-  double* st = scratch + 4 * C;
-  double* qt = scratch + 5 * C;
+__device__ __forceinline__ double F16(double q, double q0, bool act, bool is_y, double beta) {
+  const double mx = gmax16(act ? q : -INFINITY);
+  const double s = gsum16(act ? exp(q - mx) : 0.0);
+  const double qy = gsum16(is_y ? q : 0.0);
+  const double r2 = gsum16(act ? (q - q0) * (q - q0) : 0.0);
+  return mx + log(s) - qy + 0.5 * beta * r2;
+}
+
+// Prox of one sample (this lane's class): start at the previous omega-bar, stop
+// at ||grad|| <= 1e-14 or the rounding level of beta (q - Mc) if higher; returns
+// q_c / M.
+__device__ double prox_softmax_group(double cvc, double wprev, bool act, bool is_y, bool valid, int M,
+                                     double rho_l) {
   const double beta = rho_l / M;
-  for (int c = 0; c < C; ++c) {
-    q0[c] = M * cvec[c];
-    q[c] = M * w_prev[c];
-  }
-  // stop at ||grad|| <= 1e-14, or at the rounding level of beta (q - Mc) if higher
-  double qmax = 0.0;
-  for (int c = 0; c < C; ++c) qmax = fmax(qmax, fabs(q0[c]));
+  const double q0 = M * cvc;
+  double q = M * wprev;
+  const double qmax0 = gmax16(act ? fabs(q0) : 0.0);
+  bool done = !valid;
   for (int it = 0; it < 100; ++it) {
-    const double gn = softmax_grad(q, q0, y, beta, C, p, g);
-    double qa = qmax;
-    for (int c = 0; c < C; ++c) qa = fmax(qa, fabs(q[c]));
-    if (!(gn > 1e-14 + 8.0 * 2.220446049250313e-16 * beta * 2.0 * qa)) break;
-    double pDp = 0.0, pDg = 0.0;
-    for (int c = 0; c < C; ++c) {
-      const double d = 1.0 / (p[c] + beta);
-      pDp += p[c] * p[c] * d;
-      pDg += p[c] * g[c] * d;
-    }
+    const LseGrad lg = lse_grad16(q, q0, act, is_y, beta);
+    const double qa = fmax(qmax0, gmax16(act ? fabs(q) : 0.0));
+    if (!(lg.gn > 1e-14 + 8.0 * 2.220446049250313e-16 * beta * 2.0 * qa)) done = true;
+    if (__ballot(!done) == 0) break;
+    const double d = act ? 1.0 / (lg.p + beta) : 0.0;
+    const double pDp = gsum16(lg.p * lg.p * d);
+    const double pDg = gsum16(lg.p * lg.g * d);
     const double coef = pDg / (1.0 - pDp);
-    double slope = 0.0;
-    for (int c = 0; c < C; ++c) {
-      const double d = 1.0 / (p[c] + beta);
-      st[c] = d * g[c] + d * p[c] * coef;
-      slope += g[c] * st[c];
-    }
-    const double f0 = softmax_F(q, q0, y, beta, C);
+    const double st = act ? d * lg.g + d * lg.p * coef : 0.0;
+    const double slope = gsum16(lg.g * st);
+    const double f0 = F16(q, q0, act, is_y, beta);
     double t = 1.0;
+    bool acc = done;
     for (int ls = 0; ls < 60; ++ls) {
-      for (int c = 0; c < C; ++c) qt[c] = q[c] - t * st[c];
-      if (softmax_F(qt, q0, y, beta, C) <= f0 - 1e-4 * t * slope) break;
+      const double qt = q - t * st;
+      if (!acc) {
+        if (F16(qt, q0, act, is_y, beta) <= f0 - 1e-4 * t * slope) acc = true;
+      } else {
+        (void)F16(qt, q0, act, is_y, beta);  // keeps every lane in the group operations
+      }
+      const LseGrad gt = lse_grad16(qt, q0, act, is_y, beta);
       // gradient-norm decrease (F flat to rounding near the optimum)
-      if (softmax_grad(qt, q0, y, beta, C, p, g) < gn) break;
-      t *= 0.5;
+      if (!acc && gt.gn < lg.gn) acc = true;
+      if (__ballot(!acc) == 0) break;
+      if (!acc) t *= 0.5;
     }
-    for (int c = 0; c < C; ++c) q[c] = q[c] - t * st[c];
+    if (!done) q = q - t * st;
   }
-  for (int c = 0; c < C; ++c) w[c] = q[c] / M;
+  return q / M;
 }
 
 template <typename T, int NT, int NF, int R, int CC>
@@ -116,7 +128,6 @@ __global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
   constexpr int FLUSH = 16;
   __shared__ double red[NW][R][CC];
   __shared__ double e_sh[R][CC];
-  __shared__ double scratch[R][7 * CC];
 
   const int C = a.C;
   const int part = blockIdx.x / a.Gp;
@@ -174,37 +185,36 @@ __global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
       }
     }
     __syncthreads();
-    if (tid < R) {
-      const int r = tid;
+    if (tid < 64) {
+      // wavefront 0: 16-lane group r handles row rt + r, lane c of it class c
+      const int r = lane >> 4, c = lane & 15;
       const int64_t row = rt + r;
-      if (row < m) {
-        const int64_t gr = r0 + row;
-        double* cv = &scratch[r][6 * CC];   // c = a + nu (C values)
-        double av[CC];
+      const bool valid = r < R && row < m;
+      const bool act = valid && c < C;
+      const int64_t gr = r0 + (valid ? row : 0);
+      double av = 0.0;
+      if (act) {
+        double sacc = 0.0;
 #pragma unroll
-        for (int c = 0; c < CC; ++c) {
-          double s = 0.0;
-#pragma unroll
-          for (int w = 0; w < NW; ++w) s += red[w][r][c];
-          av[c] = s * a.inv_M;
-        }
-        if (a.mode == 0) {
-          for (int c = 0; c < C; ++c) cv[c] = av[c] + a.nu[gr * C + c];
-          double om[CC];
-          prox_softmax_row(cv, a.omega + gr * C, a.y[gr], a.M, a.rho_l, C, &scratch[r][0], om);
-          for (int c = 0; c < C; ++c) {
-            const double nu = a.nu[gr * C + c] + av[c] - om[c];
-            a.omega[gr * C + c] = om[c];
-            a.nu[gr * C + c] = nu;
-            e_sh[r][c] = om[c] - av[c] - nu;
-          }
-        } else {
-          for (int c = 0; c < C; ++c) e_sh[r][c] = a.omega[gr * C + c] - av[c] - a.nu[gr * C + c];
-        }
-        for (int c = C; c < CC; ++c) e_sh[r][c] = 0.0;
-      } else {
-        for (int c = 0; c < CC; ++c) e_sh[r][c] = 0.0;
+        for (int w = 0; w < NW; ++w) sacc += red[w][r][c];
+        av = sacc * a.inv_M;
       }
+      const double nu0 = act ? a.nu[gr * C + c] : 0.0;
+      const double om0 = act ? a.omega[gr * C + c] : 0.0;
+      double e = 0.0;
+      if (a.mode == 0) {
+        const bool is_y = act && a.y[gr] == c;
+        const double om = prox_softmax_group(av + nu0, om0, act, is_y, valid, a.M, a.rho_l);
+        if (act) {
+          const double nu = nu0 + av - om;
+          a.omega[gr * C + c] = om;
+          a.nu[gr * C + c] = nu;
+          e = om - av - nu;
+        }
+      } else if (act) {
+        e = om0 - av - nu0;
+      }
+      if (r < R && c < CC) e_sh[r][c] = e;
     }
     __syncthreads();
 #pragma unroll

@@ -174,13 +174,191 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
       }
 }
 
-hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s) {
-  dim3 grid(a.tiles_max * (a.tiles_max + 1) / 2, a.N * a.M);
-  switch (dtype) {
-    case BCA_F64: hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, a); break;
-    case BCA_F32: hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(gram_kernel<bf16_t>, grid, dim3(256), 0, s, a); break;
+// FP32 / BF16 Gram with 128 x 128 output tiles (4 wavefronts of 64 x 64, each a
+// 4 x 4 grid of 16 x 16 MFMA tiles) and double-buffered LDS: while the MFMAs run
+// on one KB-row chunk, the next chunk is loaded from HBM into registers.  LDS
+// holds the panels row-major, exactly as in HBM (16-byte stores, no transpose);
+// since G = sum_k a_k a_k^T may take its rows in any order, the 8 contraction
+// rows of lane group g = lane / 16 in a BF16 MFMA are rows g, g + 4, ..., g + 28
+// of the 32-row step, gathered with 2-byte LDS reads (column lane % 16).  Row
+// padding of 16 elements puts the four groups' reads in distinct banks.
+template <typename T>
+struct Gram2;
+template <>
+struct Gram2<float> {
+  using lds_t = float;
+  using vec_t = float4;
+  static constexpr int KB = 32;         // rows per chunk
+  static constexpr int K_STEP = 4;      // contraction rows per MFMA
+  static constexpr int EPV = 4;         // elements per 16-byte load
+  // operand of lane group g, column c, of the K_STEP-row step at row ks
+  __device__ static float operand(const float* p, int ks, int g, int c, int ls) {
+    return p[(ks + g) * ls + c];
   }
+  __device__ static void mma(floatx4& acc, float a, float b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+};
+template <>
+struct Gram2<bf16_t> {
+  using lds_t = uint16_t;
+  using vec_t = uint4;
+  static constexpr int KB = 64;
+  static constexpr int K_STEP = 32;
+  static constexpr int EPV = 8;
+  __device__ static bf16x8 operand(const uint16_t* p, int ks, int g, int c, int ls) {
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, p[(ks + g + 4 * e) * ls + c]);
+    return v;
+  }
+  __device__ static void mma(floatx4& acc, const bf16x8& a, const bf16x8& b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram128_kernel(GramArgs a) {
+  using G = Gram2<T>;
+  using L = typename G::lds_t;
+  using V = typename G::vec_t;
+  constexpr int KB = G::KB;
+  constexpr int LS = 128 + 16;                    // LDS row stride (elements)
+  constexpr int VPR = 128 / G::EPV;               // 16-byte vectors per panel row
+  constexpr int NV = KB * VPR / 256;              // vectors per thread per panel and chunk
+  __shared__ __attribute__((aligned(16))) L lds[2][2][KB * LS];   // [buffer][panel I/J]
+
+  const int bid = blockIdx.y;
+  const int part = bid / a.M, blk = bid - part * a.M;
+  const int c0 = a.col_off[blk];
+  const int nj = a.col_off[blk + 1] - c0;
+  const int T_ = (nj + 127) / 128;
+  int ti, tj;
+  tri_tile(blockIdx.x, &ti, &tj);
+  if (ti >= T_) return;
+  const int64_t r0 = a.row_off[part];
+  const int64_t m = a.row_off[part + 1] - r0;
+  const T* Ab = reinterpret_cast<const T*>(a.A) + r0 * a.ld + c0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  const bool diag = (ti == tj);
+
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // rows start at multiples of ld (a multiple of 64 elements), so the alignment
+  // of every vector of the block follows from its first column
+  const bool align16 = (c0 % G::EPV) == 0;
+  const bool align4 = ((c0 * (int)sizeof(T)) % 4) == 0;
+  // staging: vector q of this thread covers chunk row k = idx / VPR, columns
+  // EPV * (idx % VPR) .. + EPV - 1 of the panel (idx = tid + 256 q)
+  V stg[2][NV];
+  auto load_chunk = [&](int64_t k0) {
+#pragma unroll
+    for (int pnl = 0; pnl < 2; ++pnl) {
+      if (pnl == 1 && diag) break;
+      const int tcol = (pnl == 0 ? ti : tj) * 128;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int idx = tid + 256 * q;
+        const int k = idx / VPR, cv = idx % VPR;
+        const int64_t row = k0 + k;
+        const int col = tcol + G::EPV * cv;
+        V v;
+        __builtin_memset(&v, 0, sizeof(v));
+        if (row < m) {
+          const T* src = Ab + row * a.ld + col;
+          if (col + G::EPV <= nj && align16) {
+            v = *reinterpret_cast<const V*>(src);
+          } else if (col + G::EPV <= nj && align4) {
+            // block start not 16-byte aligned: four dword loads
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[i] = reinterpret_cast<const uint32_t*>(src)[i];
+            __builtin_memcpy(&v, w, sizeof(v));
+          } else {
+            L tmp[G::EPV];
+#pragma unroll
+            for (int e = 0; e < G::EPV; ++e) tmp[e] = L(0);
+            for (int e = 0; e < G::EPV; ++e)
+              if (col + e < nj) tmp[e] = __builtin_bit_cast(L, src[e]);
+            __builtin_memcpy(&v, tmp, sizeof(v));
+          }
+        }
+        stg[pnl][q] = v;
+      }
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int pnl = 0; pnl < 2; ++pnl) {
+      if (pnl == 1 && diag) break;
+      L* dst = lds[buf][pnl];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int idx = tid + 256 * q;
+        const int k = idx / VPR, cv = idx % VPR;
+        *reinterpret_cast<V*>(dst + k * LS + G::EPV * cv) = stg[pnl][q];
+      }
+    }
+  };
+
+  const int64_t nchunks = (m + KB - 1) / KB;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  const int g = lane >> 4, cl = lane & 15;
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int buf = (int)(ch & 1);
+    if (ch + 1 < nchunks) load_chunk((ch + 1) * KB);
+    const L* pI = lds[buf][0];
+    const L* pJ = diag ? lds[buf][0] : lds[buf][1];
+#pragma unroll
+    for (int ks = 0; ks < KB; ks += G::K_STEP) {
+      decltype(G::operand(pI, 0, 0, 0, LS)) opa[4], opb[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) opa[x] = G::operand(pI, ks, g, wr * 64 + x * 16 + cl, LS);
+#pragma unroll
+      for (int y = 0; y < 4; ++y) opb[y] = G::operand(pJ, ks, g, wc * 64 + y * 16 + cl, LS);
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) G::mma(acc[x][y], opa[x], opb[y]);
+    }
+    if (ch + 1 < nchunks) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+  double* K = a.kbuf + a.kmat_off[bid];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 128 + wr * 64 + x * 16 + 4 * (lane >> 4) + v;
+        const int col = tj * 128 + wc * 64 + y * 16 + (lane & 15);
+        if (row < nj && col < nj && row >= col) {
+          const double gv = (double)acc[x][y][v];
+          K[(int64_t)row * nj + col] = a.rho_l * gv + (row == col ? a.shift : 0.0);
+        }
+      }
+}
+
+hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s) {
+  if (dtype == BCA_F64) {
+    dim3 grid(a.tiles_max * (a.tiles_max + 1) / 2, a.N * a.M);
+    hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  const int t128 = (a.tiles_max + 1) / 2;   // tiles_max counts 64-column tiles
+  dim3 grid(t128 * (t128 + 1) / 2, a.N * a.M);
+  if (dtype == BCA_F32)
+    hipLaunchKernelGGL(gram128_kernel<float>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(gram128_kernel<bf16_t>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

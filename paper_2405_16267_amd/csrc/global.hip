@@ -9,8 +9,9 @@
 // root of the increasing piecewise-linear
 //   psi(theta) = v + theta / rho_b + sum_{k: theta_k > theta} (theta d_k^2 / a - d_k |wbar_k|),
 //   d_k = 1 - sign(wbar_k) s_k,  theta_k = a |wbar_k| / d_k (breakpoints).
-// The root is bracketed by multisection until no breakpoint lies inside the
-// bracket, then read off exactly from the linear piece.
+// psi is also concave, so Newton steps from theta = 0 reach the root exactly
+// (each step is the root of the linear piece active right of the current
+// point); multisection brackets it if Newton has not settled after 32 steps.
 // T_kappa is a radix select on the bit patterns of |z_k| (FP64 bits with the
 // sign cleared, so -0 == +0), ties resolved toward the lower index.
 #include "global_impl.h"

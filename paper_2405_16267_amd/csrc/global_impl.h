@@ -112,14 +112,30 @@ __device__ uint64_t topk_threshold(const Z* z, int64_t n, int kappa, TopkShared<
       if ((key & mask) == prefix) atomicAdd(&sh.hist[(key >> d) & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int cum = 0, D = 255;
-      for (; D > 0; --D) {
-        if (cum + (int)sh.hist[D] >= need) break;
-        cum += (int)sh.hist[D];
+    if (threadIdx.x < 64) {
+      // digit D: the highest bin where the count from the top reaches `need`.
+      // Lane l sums bins 4l..4l+3; a suffix scan over lanes finds the lane
+      // whose 4 bins hold D, and that lane walks them from the top.
+      const int l = threadIdx.x;
+      int loc = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) loc += (int)sh.hist[4 * l + b];
+      int suf = loc;  // sum over lanes >= l
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_down(suf, o, 64);
+        if (l + o < 64) suf += t;
       }
-      sh.prefix = prefix | ((uint64_t)D << d);
-      sh.need = need - cum;
+      const int above = suf - loc;  // sum over lanes > l
+      if ((suf >= need && above < need) || (l == 0 && suf < need)) {
+        int cum = above, D = 4 * l + 3;
+        for (; D > 4 * l; --D) {
+          if (cum + (int)sh.hist[D] >= need) break;
+          cum += (int)sh.hist[D];
+        }
+        sh.prefix = prefix | ((uint64_t)D << d);
+        sh.need = need - cum;
+      }
     }
     __syncthreads();
     prefix = sh.prefix;
@@ -215,45 +231,100 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
     // root beyond the last breakpoint: only coordinates with d_k = 0 remain, adding 0
     theta = -v * rb;
   } else {
+    // psi is continuous, increasing and concave (terms leave the sum as theta
+    // passes their breakpoints), so Newton steps from a point left of the root
+    // stay left of it and move monotonically to it; a step is the root of the
+    // linear piece active right of the current point, theta' = (sum_A c1 - v) /
+    // (1/rho_b + sum_A c2) with A = {k : theta_k > theta}, and it is exact once A
+    // no longer changes.  Newton starts at theta = 0 (psi(0) < 0 here); if it has
+    // not settled after 32 steps, multisection finishes the bracket from there.
     double lo = 0.0, hi = hi0;
-    for (int round = 0; round < 200; ++round) {
-      double acc[PS + 1];
-      double pts[PS];
+    bool isolated = false;
+    auto multisect = [&](int max_rounds) {
+      for (int round = 0; round < max_rounds; ++round) {
+        double acc[PS + 1];
+        double pts[PS];
 #pragma unroll
-      for (int p = 0; p < PS; ++p) {
-        pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PS + 1);
-        acc[p] = 0.0;
+        for (int p = 0; p < PS; ++p) {
+          pts[p] = lo + (hi - lo) * (double)(p + 1) / (double)(PS + 1);
+          acc[p] = 0.0;
+        }
+        acc[PS] = 0.0;  // breakpoints strictly inside (lo, hi)
+        for (int k = tid; k < n; k += GT) {
+          const double t = th[k];
+          const double ca = c1[k], cb = c2[k];
+#pragma unroll
+          for (int p = 0; p < PS; ++p)
+            if (t > pts[p]) acc[p] += pts[p] * cb - ca;
+          if (t > lo && t < hi) acc[PS] += 1.0;
+        }
+        block_sum_n<BT, PS + 1>(acc, shd);
+        if (acc[PS] == 0.0) {
+          isolated = true;
+          return;
+        }
+        int p = 0;
+        while (p < PS && v + pts[p] / rb + acc[p] < 0.0) ++p;
+        const double nlo = p == 0 ? lo : pts[p - 1];
+        const double nhi = p == PS ? hi : pts[p];
+        if (nlo == lo && nhi == hi) {
+          isolated = true;
+          return;
+        }
+        lo = nlo;
+        hi = nhi;
       }
-      acc[PS] = 0.0;  // breakpoints strictly inside (lo, hi)
+    };
+    // sums of c1, c2 and the count over {theta_k > x}
+    auto active = [&](double x, double (&sm)[3]) {
+      sm[0] = sm[1] = sm[2] = 0.0;
       for (int k = tid; k < n; k += GT) {
-        const double t = th[k];
-        const double ca = c1[k], cb = c2[k];
-#pragma unroll
-        for (int p = 0; p < PS; ++p)
-          if (t > pts[p]) acc[p] += pts[p] * cb - ca;
-        if (t > lo && t < hi) acc[PS] += 1.0;
+        if (th[k] > x) {
+          sm[0] += c1[k];
+          sm[1] += c2[k];
+          sm[2] += 1.0;
+        }
       }
-      block_sum_n<BT, PS + 1>(acc, shd);
-      if (acc[PS] == 0.0) break;
-      int p = 0;
-      while (p < PS && v + pts[p] / rb + acc[p] < 0.0) ++p;
-      const double nlo = p == 0 ? lo : pts[p - 1];
-      const double nhi = p == PS ? hi : pts[p];
-      if (nlo == lo && nhi == hi) break;
-      lo = nlo;
-      hi = nhi;
-    }
-    // exact root on the linear piece whose active set is {theta_k >= hi}
-    double sums[2] = {0.0, 0.0};
-    for (int k = tid; k < n; k += GT) {
-      if (th[k] >= hi) {
-        sums[0] += c1[k];
-        sums[1] += c2[k];
+      block_sum_n<BT, 3>(sm, shd);
+    };
+    multisect(0);
+    bool done = false;
+    if (!isolated) {
+      double cur = lo, sm[3];
+      active(cur, sm);
+      for (int it = 0; it < 32 && !done; ++it) {
+        double nx = (sm[0] - v) / (1.0 / rb + sm[1]);
+        nx = fmin(fmax(nx, cur), hi);
+        double sn[3];
+        active(nx, sn);
+        if (sn[2] == sm[2]) {
+          theta = nx;
+          done = true;
+        } else {
+          cur = nx;
+          sm[0] = sn[0];
+          sm[1] = sn[1];
+          sm[2] = sn[2];
+        }
+      }
+      if (!done) {
+        lo = cur;
+        multisect(200);
       }
     }
-    block_sum_n<BT, 2>(sums, shd);
-    theta = (sums[0] - v) / (1.0 / rb + sums[1]);
-    theta = fmin(fmax(theta, lo), hi);
+    if (!done) {
+      // exact root on the linear piece whose active set is {theta_k >= hi}
+      double sums[2] = {0.0, 0.0};
+      for (int k = tid; k < n; k += GT) {
+        if (th[k] >= hi) {
+          sums[0] += c1[k];
+          sums[1] += c2[k];
+        }
+      }
+      block_sum_n<BT, 2>(sums, shd);
+      theta = (sums[0] - v) / (1.0 / rb + sums[1]);
+      theta = fmin(fmax(theta, lo), hi);
+    }
   }
   // z(theta) per row; rows of the matrix variable are scaled copies of wbar_k
   double tl = 0.0;

@@ -45,38 +45,6 @@ __global__ __launch_bounds__(256) void reduce_rhs_kernel(SolveArgs a) {
 //   TRANS = 0: row r of W, entries W[r, 0..r] at wr + r (r + 1) / 2, times in[0..r].
 //   TRANS = 1: row c of W^T, entries W[c..nj-1, c] at wc + c nj - c (c - 1) / 2,
 //              times in[c..nj-1]; the result is added to x.
-// With one right-hand side the two rows are walked together (8 loads per lane
-// in flight); each row's sum keeps its own fixed order.
-template <int TRANS>
-__device__ __forceinline__ void trmv_row_span(int r, int nj, int64_t* off, int* st, int* len) {
-  if (!TRANS) {
-    *off = (int64_t)r * (r + 1) / 2;
-    *st = 0;
-    *len = r + 1;
-  } else {
-    *off = (int64_t)r * nj - (int64_t)r * (r - 1) / 2;
-    *st = r;
-    *len = nj - r;
-  }
-}
-
-template <int TRANS>
-__device__ __forceinline__ void trmv_store(const SolveArgs& a, double* out, int part, int c0, int r, int C,
-                                          int c, double tot) {
-  const int64_t o = ((int64_t)part * a.n + c0 + r) * C + c;
-  if (!TRANS) {
-    out[o] = tot;
-  } else {
-    const double xn = a.x[o] + tot;
-    a.xw[o] = xn;
-    const int64_t so = (int64_t)part * a.ld * C + (int64_t)(c0 + r) * C + c;
-    if (a.xs_f64)
-      reinterpret_cast<double*>(a.xs)[so] = xn;
-    else
-      reinterpret_cast<float*>(a.xs)[so] = (float)xn;
-  }
-}
-
 template <int TRANS, int CC>
 __global__ __launch_bounds__(256) void trmv_kernel(SolveArgs a, const double* in, double* out) {
   const int bid = blockIdx.y;
@@ -90,43 +58,35 @@ __global__ __launch_bounds__(256) void trmv_kernel(SolveArgs a, const double* in
   const int C = CC == 1 ? 1 : a.C;
   const double* F = (TRANS ? a.wc : a.wr) + a.fac_off[bid];
   const double* v = in + ((int64_t)part * a.n + c0) * C;
-  if constexpr (CC == 1) {
-    const int rA = pr, rB = nj - 1 - pr;
-    const bool two = rB != rA;
-    int64_t offA, offB;
-    int stA, lenA, stB, lenB;
-    trmv_row_span<TRANS>(rA, nj, &offA, &stA, &lenA);
-    trmv_row_span<TRANS>(rB, nj, &offB, &stB, &lenB);
-    if (!two) lenB = 0;
-    const double* fA = F + offA;
-    const double* fB = F + offB;
-    const double* vA = v + stA;
-    const double* vB = v + stB;
-    double sA[4] = {0.0, 0.0, 0.0, 0.0}, sB[4] = {0.0, 0.0, 0.0, 0.0};
-    const int len = lenA > lenB ? lenA : lenB;
-    for (int e0 = 0; e0 < len; e0 += 256) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + 64 * u + lane;
-        if (e < lenA) sA[u] += fA[e] * vA[e];
-        if (e < lenB) sB[u] += fB[e] * vB[e];
+  for (int h = 0; h < 2; ++h) {
+    const int r = h == 0 ? pr : nj - 1 - pr;
+    if (h == 1 && r == pr) break;
+    int64_t off;
+    int st, len;
+    if (!TRANS) {
+      off = (int64_t)r * (r + 1) / 2;
+      st = 0;
+      len = r + 1;
+    } else {
+      off = (int64_t)r * nj - (int64_t)r * (r - 1) / 2;
+      st = r;
+      len = nj - r;
+    }
+    const double* f = F + off;
+    double tot[CC];
+    if (CC == 1) {
+      const double* vv = v + st;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int e = lane;
+      for (; e + 192 < len; e += 256) {
+        s0 += f[e] * vv[e];
+        s1 += f[e + 64] * vv[e + 64];
+        s2 += f[e + 128] * vv[e + 128];
+        s3 += f[e + 192] * vv[e + 192];
       }
-    }
-    const double tA = wave_sum((sA[0] + sA[1]) + (sA[2] + sA[3]));
-    const double tB = wave_sum((sB[0] + sB[1]) + (sB[2] + sB[3]));
-    if (lane == 0) {
-      trmv_store<TRANS>(a, out, part, c0, rA, 1, 0, tA);
-      if (two) trmv_store<TRANS>(a, out, part, c0, rB, 1, 0, tB);
-    }
-    return;
-  } else {
-    for (int h = 0; h < 2; ++h) {
-      const int r = h == 0 ? pr : nj - 1 - pr;
-      if (h == 1 && r == pr) break;
-      int64_t off;
-      int st, len;
-      trmv_row_span<TRANS>(r, nj, &off, &st, &len);
-      const double* f = F + off;
+      for (; e < len; e += 64) s0 += f[e] * vv[e];
+      tot[0] = wave_sum((s0 + s1) + (s2 + s3));
+    } else {
       double sc[CC];
 #pragma unroll
       for (int c = 0; c < CC; ++c) sc[c] = 0.0;
@@ -137,11 +97,24 @@ __global__ __launch_bounds__(256) void trmv_kernel(SolveArgs a, const double* in
         for (int c = 0; c < CC; ++c)
           if (c < C) sc[c] += fe * vv[c];
       }
-      double tot[CC];
 #pragma unroll
       for (int c = 0; c < CC; ++c) tot[c] = wave_sum(sc[c]);
-      if (lane == 0)
-        for (int c = 0; c < C; ++c) trmv_store<TRANS>(a, out, part, c0, r, C, c, tot[c]);
+    }
+    if (lane == 0) {
+      for (int c = 0; c < C; ++c) {
+        const int64_t o = ((int64_t)part * a.n + c0 + r) * C + c;
+        if (!TRANS) {
+          out[o] = tot[c];
+        } else {
+          const double xn = a.x[o] + tot[c];
+          a.xw[o] = xn;
+          const int64_t so = (int64_t)part * a.ld * C + (int64_t)(c0 + r) * C + c;
+          if (a.xs_f64)
+            reinterpret_cast<double*>(a.xs)[so] = xn;
+          else
+            reinterpret_cast<float*>(a.xs)[so] = (float)xn;
+        }
+      }
     }
   }
 }

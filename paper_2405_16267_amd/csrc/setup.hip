@@ -363,112 +363,141 @@ hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ Cholesky
-__global__ __launch_bounds__(256) void cholesky_kernel(FactorArgs a) {
-  __shared__ double D[32][33];
-  __shared__ double P0[64][33];
-  __shared__ double P1[64][33];
+// Right-looking blocked Cholesky of all N M blocks at once, one 32-column panel
+// per step and three launches per step so that every workgroup of the GPU
+// takes part: the diagonal 32 x 32 block (one workgroup per matrix), the panel
+// below it (one thread per row), and the trailing update of the lower 64 x 64
+// tiles (one workgroup per tile and matrix).
+constexpr int CHB = 32;
+
+__global__ __launch_bounds__(256) void chol_diag_kernel(FactorArgs a, int k0) {
+  __shared__ double D[CHB][CHB + 1];
   const int bid = blockIdx.x;
   const int blk = bid % a.M;
   const int n = a.col_off[blk + 1] - a.col_off[blk];
+  if (k0 >= n) return;
   double* K = a.kbuf + a.kmat_off[bid];
   const int tid = threadIdx.x;
-
-  for (int k0 = 0; k0 < n; k0 += 32) {
-    const int kb = min(32, n - k0);
-    for (int idx = tid; idx < 32 * 32; idx += 256) {
-      const int r = idx >> 5, c = idx & 31;
-      D[r][c] = (r < kb && c <= r) ? K[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
+  const int kb = min(CHB, n - k0);
+  for (int idx = tid; idx < CHB * CHB; idx += 256) {
+    const int r = idx / CHB, c = idx % CHB;
+    D[r][c] = (r < kb && c <= r) ? K[(int64_t)(k0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int p = 0; p < kb; ++p) {
+    if (tid == 0) {
+      double d = D[p][p];
+      if (!(d > 0.0) || !isfinite(d)) {
+        atomicExch(a.status, 1);
+        d = 1.0;
+      }
+      D[p][p] = sqrt(d);
     }
     __syncthreads();
-    // unblocked factorisation of the diagonal block
-    for (int p = 0; p < kb; ++p) {
-      if (tid == 0) {
-        double d = D[p][p];
-        if (!(d > 0.0) || !isfinite(d)) {
-          atomicExch(a.status, 1);
-          d = 1.0;
-        }
-        D[p][p] = sqrt(d);
-      }
-      __syncthreads();
-      if (tid > p && tid < kb) D[tid][p] /= D[p][p];
-      __syncthreads();
-      for (int idx = tid; idx < 32 * 32; idx += 256) {
-        const int r = idx >> 5, c = idx & 31;
-        if (c > p && r >= c && r < kb) D[r][c] -= D[r][p] * D[c][p];
-      }
-      __syncthreads();
-    }
-    for (int idx = tid; idx < 32 * 32; idx += 256) {
-      const int r = idx >> 5, c = idx & 31;
-      if (r < kb && c <= r) K[(int64_t)(k0 + r) * n + k0 + c] = D[r][c];
-    }
-    // panel below the diagonal block: L[r, k0:k0+kb] = K[r, k0:k0+kb] D^-T
-    const int k1 = k0 + kb;
-    for (int r = k1 + tid; r < n; r += 256) {
-      double x[32];
-      double* row = K + (int64_t)r * n + k0;
-#pragma unroll
-      for (int p = 0; p < 32; ++p) x[p] = (p < kb) ? row[p] : 0.0;
-#pragma unroll
-      for (int p = 0; p < 32; ++p) {
-        if (p < kb) {
-          double v = x[p];
-#pragma unroll
-          for (int q = 0; q < 32; ++q)
-            if (q < p) v -= x[q] * D[p][q];
-          x[p] = v / D[p][p];
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < 32; ++p)
-        if (p < kb) row[p] = x[p];
+    if (tid > p && tid < kb) D[tid][p] /= D[p][p];
+    __syncthreads();
+    for (int idx = tid; idx < CHB * CHB; idx += 256) {
+      const int r = idx / CHB, c = idx % CHB;
+      if (c > p && r >= c && r < kb) D[r][c] -= D[r][p] * D[c][p];
     }
     __syncthreads();
-    // trailing update K[r, c] -= sum_p L[r, p] L[c, p], k1 <= c <= r < n
-    const int nt = (n - k1 + 63) / 64;
-    const int ty = tid >> 4, tx = tid & 15;
-    for (int t = 0; t < nt * (nt + 1) / 2; ++t) {
-      int ti = 0;
-      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-      const int tj = t - ti * (ti + 1) / 2;
-      for (int idx = tid; idx < 64 * 32; idx += 256) {
-        const int r = idx >> 5, p = idx & 31;
-        const int gi = k1 + ti * 64 + r, gj = k1 + tj * 64 + r;
-        P0[r][p] = (gi < n && p < kb) ? K[(int64_t)gi * n + k0 + p] : 0.0;
-        P1[r][p] = (gj < n && p < kb) ? K[(int64_t)gj * n + k0 + p] : 0.0;
-      }
-      __syncthreads();
-      double acc[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-      for (int p = 0; p < kb; ++p) {
-        double li[4], lj[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) li[x] = P0[ty + 16 * x][p];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) lj[y] = P1[tx + 16 * y][p];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * lj[y];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int gi = k1 + ti * 64 + ty + 16 * x, gj = k1 + tj * 64 + tx + 16 * y;
-          if (gi < n && gj <= gi) K[(int64_t)gi * n + gj] -= acc[x][y];
-        }
-      __syncthreads();
-    }
+  }
+  for (int idx = tid; idx < CHB * CHB; idx += 256) {
+    const int r = idx / CHB, c = idx % CHB;
+    if (r < kb && c <= r) K[(int64_t)(k0 + r) * n + k0 + c] = D[r][c];
   }
 }
 
+// rows r >= k0 + 32: L[r, k0:k0+kb] = K[r, k0:k0+kb] D^-T (forward substitution)
+__global__ __launch_bounds__(256) void chol_panel_kernel(FactorArgs a, int k0) {
+  __shared__ double D[CHB][CHB + 1];
+  const int bid = blockIdx.y;
+  const int blk = bid % a.M;
+  const int n = a.col_off[blk + 1] - a.col_off[blk];
+  const int k1 = k0 + CHB;
+  if (k1 >= n) return;
+  const int r = k1 + blockIdx.x * 256 + threadIdx.x;
+  if (k1 + blockIdx.x * 256 >= n) return;
+  double* K = a.kbuf + a.kmat_off[bid];
+  for (int idx = threadIdx.x; idx < CHB * CHB; idx += 256) {
+    const int i = idx / CHB, j = idx % CHB;
+    D[i][j] = j <= i ? K[(int64_t)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  if (r >= n) return;
+  double x[CHB];
+  double* row = K + (int64_t)r * n + k0;
+#pragma unroll
+  for (int p = 0; p < CHB; ++p) x[p] = row[p];
+#pragma unroll
+  for (int p = 0; p < CHB; ++p) {
+    double v = x[p];
+#pragma unroll
+    for (int q = 0; q < p; ++q) v -= x[q] * D[p][q];
+    x[p] = v / D[p][p];
+  }
+#pragma unroll
+  for (int p = 0; p < CHB; ++p) row[p] = x[p];
+}
+
+// K[r, c] -= sum_p L[r, p] L[c, p] over the lower 64 x 64 tiles of the trailing part
+__global__ __launch_bounds__(256) void chol_update_kernel(FactorArgs a, int k0) {
+  __shared__ double P0[64][CHB + 1];
+  __shared__ double P1[64][CHB + 1];
+  const int bid = blockIdx.y;
+  const int blk = bid % a.M;
+  const int n = a.col_off[blk + 1] - a.col_off[blk];
+  const int k1 = k0 + CHB;
+  if (k1 >= n) return;
+  const int nt = (n - k1 + 63) / 64;
+  int ti, tj;
+  tri_tile(blockIdx.x, &ti, &tj);
+  if (ti >= nt) return;
+  double* K = a.kbuf + a.kmat_off[bid];
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int idx = tid; idx < 64 * CHB; idx += 256) {
+    const int r = idx / CHB, p = idx % CHB;
+    const int gi = k1 + ti * 64 + r, gj = k1 + tj * 64 + r;
+    P0[r][p] = gi < n ? K[(int64_t)gi * n + k0 + p] : 0.0;
+    P1[r][p] = gj < n ? K[(int64_t)gj * n + k0 + p] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+#pragma unroll 8
+  for (int p = 0; p < CHB; ++p) {
+    double li[4], lj[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) li[x] = P0[ty + 16 * x][p];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) lj[y] = P1[tx + 16 * y][p];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * lj[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int gi = k1 + ti * 64 + ty + 16 * x, gj = k1 + tj * 64 + tx + 16 * y;
+      if (gi < n && gj <= gi) K[(int64_t)gi * n + gj] -= acc[x][y];
+    }
+}
+
 hipError_t launch_cholesky(const FactorArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(cholesky_kernel, dim3(a.N * a.M), dim3(256), 0, s, a);
+  const int nm = a.N * a.M;
+  for (int k0 = 0; k0 < a.nj_max; k0 += CHB) {
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(nm), dim3(256), 0, s, a, k0);
+    const int rest = a.nj_max - k0 - CHB;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3((rest + 255) / 256, nm), dim3(256), 0, s, a, k0);
+    const int nt = (rest + 63) / 64;
+    hipLaunchKernelGGL(chol_update_kernel, dim3(nt * (nt + 1) / 2, nm), dim3(256), 0, s, a, k0);
+  }
   return hipGetLastError();
 }
 

@@ -7,8 +7,8 @@ GPU library can both be fed from it without sharing any code.
 
 Recipes follow the experimental section of the paper (dense Gaussian feature
 matrices with per-node unit-norm columns, a planted sparse ground truth, noisy
-linear targets); the logistic, softmax and batched recipes are the synthetic
-workloads described in the design doc (AR(1) rows with Toeplitz covariance 0.3^|i-j|,
+linear targets); the logistic, softmax and batched recipes are synthetic
+workloads of the same kind (AR(1) rows with Toeplitz covariance 0.3^|i-j|,
 Bernoulli-logit labels, argmax-plus-Gumbel class labels).
 
 Random numbers are Philox4x32-10 (Salmon et al., SC 2011) addressed by

@@ -22,7 +22,7 @@ Everything is FP64.  The steps are taken in the paper's order and notation:
   omega-bar prox and the nu dual update;
 * termination residuals p_r, d_r, b_r (Sec. 3, Termination).
 
-Readings where the paper is silent or inconsistent (all listed in the design doc):
+Readings where the paper is silent or inconsistent:
   - scaled consensus form as printed: x_i = prox(z - u_i), u_i += x_i - z, so the
     (z, t) target is w = mean_i (x_i + u_i);
   - the (z, t) step is solved exactly (unique minimiser of a strictly convex

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances (the design doc derives them): FP64 storage 1e-12 relative on
+Tolerances: FP64 storage 1e-12 relative on
 coefficients and objective; FP32 storage 1e-5 relative (norm-wise) on
 coefficients and objective; supports and top-kappa selections bit-exact whenever
 the oracle's top-kappa margin is wider than the precision's error bound.

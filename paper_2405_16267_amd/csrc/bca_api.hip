@@ -72,6 +72,7 @@ struct bca_problem_s {
   double* b = nullptr;
   int32_t* y = nullptr;
   double *omega = nullptr, *nu = nullptr;
+  double* rowbuf = nullptr;   // m_total x C, multi-class pass (averages, then e)
   double *x = nullptr, *u = nullptr, *rhs = nullptr, *tmp = nullptr;
   void* xs = nullptr;
   void* xhat_s = nullptr;
@@ -217,6 +218,8 @@ StreamArgs stream_args(bca_problem P, int mode) {
   a.nu = P->nu;
   a.xs = P->xs;
   a.gpart = P->gpart;
+  a.rowbuf = P->rowbuf;
+  a.m_total = P->m_total;
   a.N = P->N;
   a.Gp = P->Gp;
   a.nvec = P->nvec;
@@ -392,11 +395,15 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
       cus = prop.multiProcessorCount;
-    const int occ = stream_occupancy_workgroups(P->dtype, P->nvec, C);
+    const int occ = C > 1 ? mc_occupancy_workgroups(P->dtype, P->n, C)
+                          : stream_occupancy_workgroups(P->dtype, P->nvec, C);
     int64_t gp = (int64_t)occ * cus / P->N;
     int64_t maxrows = 0;
     for (auto r : P->rows) maxrows = std::max(maxrows, r);
-    gp = std::min<int64_t>(gp, (maxrows + 3) / 4);
+    // at least one 4-row tile per workgroup; with C > 1 at least 16 tiles, since
+    // a workgroup's partial sums (n x C doubles) would otherwise outweigh the
+    // rows of A it streams
+    gp = std::min<int64_t>(gp, (maxrows + (C > 1 ? 63 : 3)) / (C > 1 ? 64 : 4));
     P->Gp = (int)std::max<int64_t>(1, gp);
   }
   P->loaded.assign(P->N, 0);
@@ -421,6 +428,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   }
   if (rc == BCA_OK) chk(dalloc(P, &P->omega, (size_t)P->m_total * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->nu, (size_t)P->m_total * C));
+  if (rc == BCA_OK && C > 1) chk(dalloc(P, &P->rowbuf, (size_t)P->m_total * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->x, (size_t)P->N * P->n * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->u, (size_t)P->N * P->n * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->rhs, (size_t)P->N * P->n * C));

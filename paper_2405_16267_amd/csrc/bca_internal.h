@@ -98,6 +98,8 @@ struct StreamArgs {
   double* nu;              // m_total x C
   const void* xs;          // N x ld x C streaming copy of x (FP64 or FP32)
   double* gpart;           // N x Gp x ld x C partial sums of A^T e
+  double* rowbuf;          // m_total x C (C > 1): sample-space averages, then e
+  int64_t m_total;
   int N, Gp, nvec, n, M, C, loss;
   double inv_M, rho_l;
   int mode;                // 0: inner iteration; 1: prime (e from stored state, no prox)
@@ -119,6 +121,8 @@ struct Problem;  // host-side problem (bca_api.hip)
 
 // Launchers (host side).  Each returns hipSuccess or the launch error.
 hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s);
+// Resident workgroups per CU of the multi-class streaming kernels (C > 1).
+int mc_occupancy_workgroups(int dtype, int n, int C);
 hipError_t launch_objective(const ObjArgs& a, int dtype, hipStream_t s);
 // C > 1 (softmax) forms of the two passes (stream_mc.hip)
 bool mc_supported(int n, int C);

@@ -7,7 +7,8 @@
 // and factorisation, zero state).  Every scheduler round advances ALL resident
 // requests together -- one-class requests by `round_iters` outer iterations of
 // the batched persistent launch, softmax requests by the same number of
-// iterations of their own kernels -- then retires the finished ones (results
+// iterations of their own kernels, spread over three extra streams so that
+// the kernels of different requests overlap -- then retires the finished ones (results
 // copied to host, device memory released) so that waiting requests can enter
 // between rounds.  A request's arithmetic never depends on the other requests
 // it shares rounds with, so its result is the same alone and in any mix.
@@ -66,7 +67,7 @@ size_t footprint(const bca_params& p, const std::vector<int64_t>& rows) {
   const int64_t N = p.n_partitions, M = p.n_blocks;
   const int64_t nj = (n + M - 1) / M;
   size_t b = (size_t)m * ld * esize(p.a_dtype);       // A
-  b += (size_t)m * 8 * (1 + 2 * C);                   // b, omega, nu
+  b += (size_t)m * 8 * (1 + 2 * C + (C > 1 ? C : 0));  // b, omega, nu (and the multi-class row buffer)
   b += (size_t)N * n * C * 8 * 4 + (size_t)N * ld * C * 8;   // x, u, rhs, tmp, xs
   b += (size_t)N * M * nj * (nj + 1) * 8;             // packed inverse factors (two copies)
   b += (size_t)N * M * nj * nj * 8 * 2;               // finalize work space (released after)
@@ -79,10 +80,18 @@ size_t footprint(const bca_params& p, const std::vector<int64_t>& rows) {
 
 }  // namespace
 
+// Softmax requests run their own kernels; they are spread over a few extra
+// streams (default priority) so that the kernels of different requests, each
+// too small to fill the GPU, overlap.
+constexpr int kSideStreams = 3;
+
 struct bca_server_s {
   size_t budget = 0, used = 0;
   int max_slots = 1, round_iters = 1;
+  int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side[kSideStreams] = {nullptr, nullptr, nullptr};
+  uint64_t side_next = 0;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
@@ -117,7 +126,9 @@ void finish(bca_server_s* S, Request* r, int state, const std::string& err) {
 int materialise(bca_server_s* S, Request* r) {
   bca_params p = r->params;
   p.rows = r->rows.data();
-  int rc = bca_create(&p, S->stream, &r->prob);
+  hipStream_t st = S->stream;
+  if (p.loss == BCA_LOSS_SOFTMAX && S->side[0]) st = S->side[S->side_next++ % kSideStreams];
+  int rc = bca_create(&p, st, &r->prob);
   if (rc != BCA_OK) return rc;
   for (int i = 0; i < p.n_partitions; ++i) {
     rc = bca_set_data(r->prob, i, r->A[i].data(), p.n_features, r->b[i].data(), BCA_MEM_HOST);
@@ -139,6 +150,7 @@ int collect(Request* r) {
 }
 
 void scheduler(bca_server_s* S) {
+  (void)hipSetDevice(S->device);
   for (;;) {
     std::vector<Request*> admitted;
     {
@@ -207,6 +219,8 @@ void scheduler(bca_server_s* S) {
       }
     }
     (void)hipStreamSynchronize(S->stream);
+    for (int q = 0; q < kSideStreams; ++q)
+      if (S->side[q]) (void)hipStreamSynchronize(S->side[q]);
     // retire finished, failed and cancelled requests
     std::vector<Request*> keep;
     for (Request* r : act) {
@@ -257,6 +271,17 @@ int bca_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t round_
   S->max_slots = max_slots;
   S->round_iters = round_iters;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    delete S;
+    return BCA_E_DEVICE;
+  }
+  for (int q = 0; q < kSideStreams; ++q) {
+    if (hipStreamCreate(&S->side[q]) != hipSuccess) {
+      for (int j = 0; j < q; ++j) (void)hipStreamDestroy(S->side[j]);
+      delete S;
+      return BCA_E_DEVICE;
+    }
+  }
   S->worker = std::thread(scheduler, S);
   *out = S;
   return BCA_OK;
@@ -349,6 +374,8 @@ int bca_server_destroy(bca_server S) {
   if (S->worker.joinable()) S->worker.join();
   for (Request* r : S->active)
     if (r->prob) bca_destroy(r->prob);
+  for (int q = 0; q < kSideStreams; ++q)
+    if (S->side[q]) (void)hipStreamDestroy(S->side[q]);
   delete S;
   return BCA_OK;
 }

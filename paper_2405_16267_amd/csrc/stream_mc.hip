@@ -4,9 +4,8 @@
 // step is a C-dimensional prox per sample and A_i^T E is n x C.  Thread t owns
 // the features t, t + NT, ..., and for each of them all C columns of X in
 // registers; the per-row dots (R rows x C classes) are reduced across the
-// workgroup, the first wavefront runs the softmax prox of the R rows (a 16-lane
-// group per row, a lane per class), and e_k (C values) is broadcast back for the
-// A_i^T E accumulation.  Tile partial sums of A_i^T E are
+// workgroup, the softmax prox runs with a 16-lane group per row and a lane per
+// class, and e_k (C values) is read back for the A_i^T E accumulation.  Tile partial sums of A_i^T E are
 // formed in the arithmetic type and folded every FLUSH tiles into the
 // workgroup's FP64 partial vector in global memory.
 //
@@ -121,13 +120,20 @@ __device__ double prox_softmax_group(double cvc, double wprev, bool act, bool is
   return q / M;
 }
 
+// The pass runs as three kernels: the C-dimensional prox of a sample costs far
+// more than streaming its row of A (n <= 2048), so it gets a kernel of its own
+// with every wavefront busy (4 samples per wavefront), between a kernel that
+// forms the sample-space averages and one that accumulates A_i^T E.  A is read
+// twice per inner iteration; both reads are cheap next to the prox.
+//   dot_mc_kernel   a_k = (1/M) A_k X   (R rows per tile, reduced over the workgroup)
+//   prox_mc_kernel  omega-bar, nu, e_k  (16-lane group per sample)
+//   acc_mc_kernel   partial sums of A_i^T E per workgroup (same tiles and
+//                   workgroups as dot_mc_kernel)
 template <typename T, int NT, int NF, int R, int CC>
-__global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
+__global__ __launch_bounds__(NT) void dot_mc_kernel(StreamArgs a) {
   using acc = typename Traits<T>::acc_t;
   constexpr int NW = NT / 64;
-  constexpr int FLUSH = 16;
   __shared__ double red[NW][R][CC];
-  __shared__ double e_sh[R][CC];
 
   const int C = a.C;
   const int part = blockIdx.x / a.Gp;
@@ -145,22 +151,8 @@ __global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
 #pragma unroll
     for (int c = 0; c < CC; ++c) xr[f][c] = (k < n && c < C) ? xs[(int64_t)k * C + c] : acc(0);
   }
-  double* gp = a.gpart + ((int64_t)part * a.Gp + wg) * a.ld * C;
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const int k = tid + f * NT;
-    if (k < n)
-      for (int c = 0; c < C; ++c) gp[(int64_t)k * C + c] = 0.0;
-  }
-  acc gt[NF][CC];
-#pragma unroll
-  for (int f = 0; f < NF; ++f)
-#pragma unroll
-    for (int c = 0; c < CC; ++c) gt[f][c] = acc(0);
-
   const T* Ab = reinterpret_cast<const T*>(a.A) + r0 * a.ld;
   const int64_t ntiles = (m + R - 1) / R;
-  int since_flush = 0;
   for (int64_t tile = wg; tile < ntiles; tile += a.Gp) {
     const int64_t rt = tile * R;
     acc v[R][NF];
@@ -185,43 +177,92 @@ __global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
       }
     }
     __syncthreads();
-    if (tid < 64) {
-      // wavefront 0: 16-lane group r handles row rt + r, lane c of it class c
-      const int r = lane >> 4, c = lane & 15;
+    if (tid < R * CC) {
+      const int r = tid / CC, c = tid % CC;
       const int64_t row = rt + r;
-      const bool valid = r < R && row < m;
-      const bool act = valid && c < C;
-      const int64_t gr = r0 + (valid ? row : 0);
-      double av = 0.0;
-      if (act) {
+      if (row < m && c < C) {
         double sacc = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sacc += red[w][r][c];
-        av = sacc * a.inv_M;
+        a.rowbuf[(r0 + row) * C + c] = sacc * a.inv_M;
       }
-      const double nu0 = act ? a.nu[gr * C + c] : 0.0;
-      const double om0 = act ? a.omega[gr * C + c] : 0.0;
-      double e = 0.0;
-      if (a.mode == 0) {
-        const bool is_y = act && a.y[gr] == c;
-        const double om = prox_softmax_group(av + nu0, om0, act, is_y, valid, a.M, a.rho_l);
-        if (act) {
-          const double nu = nu0 + av - om;
-          a.omega[gr * C + c] = om;
-          a.nu[gr * C + c] = nu;
-          e = om - av - nu;
-        }
-      } else if (act) {
-        e = om0 - av - nu0;
-      }
-      if (r < R && c < CC) e_sh[r][c] = e;
     }
     __syncthreads();
+  }
+}
+
+// One wavefront per 4 samples: 16-lane group r takes sample 4 w + r, lane c of
+// it class c.  In: rowbuf = a (averages); out: rowbuf = e.
+__global__ __launch_bounds__(256) void prox_mc_kernel(StreamArgs a) {
+  const int C = a.C;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane >> 4, c = lane & 15;
+  const int64_t gr = ((int64_t)blockIdx.x * 4 + wv) * 4 + r;
+  const bool valid = gr < a.m_total;
+  const bool act = valid && c < C;
+  const int64_t o = (valid ? gr : 0) * C + c;
+  const double av = act ? a.rowbuf[o] : 0.0;
+  const double nu0 = act ? a.nu[o] : 0.0;
+  const double om0 = act ? a.omega[o] : 0.0;
+  double e = 0.0;
+  if (a.mode == 0) {
+    const bool is_y = act && a.y[valid ? gr : 0] == c;
+    const double om = prox_softmax_group(av + nu0, om0, act, is_y, valid, a.M, a.rho_l);
+    if (act) {
+      const double nu = nu0 + av - om;
+      a.omega[o] = om;
+      a.nu[o] = nu;
+      e = om - av - nu;
+    }
+  } else if (act) {
+    e = om0 - av - nu0;
+  }
+  if (act) a.rowbuf[o] = e;
+}
+
+template <typename T, int NT, int NF, int R, int CC>
+__global__ __launch_bounds__(NT) void acc_mc_kernel(StreamArgs a) {
+  using acc = typename Traits<T>::acc_t;
+  constexpr int FLUSH = 16;
+  const int C = a.C;
+  const int part = blockIdx.x / a.Gp;
+  const int wg = blockIdx.x - part * a.Gp;
+  const int64_t r0 = a.row_off[part];
+  const int64_t m = a.row_off[part + 1] - r0;
+  const int tid = threadIdx.x;
+  const int n = a.n;
+
+  double* gp = a.gpart + ((int64_t)part * a.Gp + wg) * a.ld * C;
+  bool first = true;  // the first flush writes the partial sums, later ones add
+  acc gt[NF][CC];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int c = 0; c < CC; ++c) gt[f][c] = acc(0);
+
+  const T* Ab = reinterpret_cast<const T*>(a.A) + r0 * a.ld;
+  const int64_t ntiles = (m + R - 1) / R;
+  int since_flush = 0;
+  for (int64_t tile = wg; tile < ntiles; tile += a.Gp) {
+    const int64_t rt = tile * R;
+    acc v[R][NF];
+    double er[R][CC];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t row = rt + r;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int k = tid + f * NT;
+        v[r][f] = (row < m && k < n) ? load_scalar<T>(Ab + row * a.ld + k) : acc(0);
+      }
+#pragma unroll
+      for (int c = 0; c < CC; ++c) er[r][c] = (row < m && c < C) ? a.rowbuf[(r0 + row) * C + c] : 0.0;
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int c = 0; c < CC; ++c) {
-        const acc e = (acc)e_sh[r][c];
+        const acc e = (acc)er[r][c];
 #pragma unroll
         for (int f = 0; f < NF; ++f) gt[f][c] += e * v[r][f];
       }
@@ -233,11 +274,15 @@ __global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
         if (k < n) {
 #pragma unroll
           for (int c = 0; c < CC; ++c)
-            if (c < C) gp[(int64_t)k * C + c] += (double)gt[f][c];
+            if (c < C) {
+              double* q = gp + (int64_t)k * C + c;
+              *q = first ? (double)gt[f][c] : *q + (double)gt[f][c];
+            }
         }
 #pragma unroll
         for (int c = 0; c < CC; ++c) gt[f][c] = acc(0);
       }
+      first = false;
     }
   }
 #pragma unroll
@@ -246,7 +291,10 @@ __global__ __launch_bounds__(NT) void stream_mc_kernel(StreamArgs a) {
     if (k < n) {
 #pragma unroll
       for (int c = 0; c < CC; ++c)
-        if (c < C) gp[(int64_t)k * C + c] += (double)gt[f][c];
+        if (c < C) {
+          double* q = gp + (int64_t)k * C + c;
+          *q = first ? (double)gt[f][c] : *q + (double)gt[f][c];
+        }
     }
   }
 }
@@ -319,17 +367,62 @@ static void mc_launch(const StreamArgs& a, hipStream_t s) {
   int nt, nf;
   mc_shape(a.n, &nt, &nf);
   dim3 grid(a.N * a.Gp);
-#define BCA_MC(NT_, NF_) hipLaunchKernelGGL((stream_mc_kernel<T, NT_, NF_, 4, CC>), grid, dim3(NT_), 0, s, a)
-  if (nt == 256) {
-    if (nf == 1) BCA_MC(256, 1);
-    else if (nf == 2) BCA_MC(256, 2);
-    else BCA_MC(256, 4);
-  } else {
-    if (nf == 1) BCA_MC(512, 1);
-    else if (nf == 2) BCA_MC(512, 2);
-    else BCA_MC(512, 4);
+#define BCA_MC(K_, NT_, NF_) hipLaunchKernelGGL((K_<T, NT_, NF_, 4, CC>), grid, dim3(NT_), 0, s, a)
+#define BCA_MC_ALL(K_)                    \
+  if (nt == 256) {                        \
+    if (nf == 1) BCA_MC(K_, 256, 1);      \
+    else if (nf == 2) BCA_MC(K_, 256, 2); \
+    else BCA_MC(K_, 256, 4);              \
+  } else {                                \
+    if (nf == 1) BCA_MC(K_, 512, 1);      \
+    else if (nf == 2) BCA_MC(K_, 512, 2); \
+    else BCA_MC(K_, 512, 4);              \
   }
+  BCA_MC_ALL(dot_mc_kernel)
+  const unsigned waves = (unsigned)((a.m_total + 3) / 4);
+  hipLaunchKernelGGL(prox_mc_kernel, dim3((waves + 3) / 4), dim3(256), 0, s, a);
+  BCA_MC_ALL(acc_mc_kernel)
+#undef BCA_MC_ALL
 #undef BCA_MC
+}
+
+template <typename T, int CC>
+static int mc_occ(int n) {
+  int nt, nf;
+  mc_shape(n, &nt, &nf);
+  int b1 = 0, b2 = 0;
+#define BCA_OCC2(NT_, NF_)                                                                     \
+  do {                                                                                         \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, dot_mc_kernel<T, NT_, NF_, 4, CC>, NT_, 0) != hipSuccess) b1 = 1; \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, acc_mc_kernel<T, NT_, NF_, 4, CC>, NT_, 0) != hipSuccess) b2 = 1; \
+  } while (0)
+  if (nt == 256) {
+    if (nf == 1) BCA_OCC2(256, 1);
+    else if (nf == 2) BCA_OCC2(256, 2);
+    else BCA_OCC2(256, 4);
+  } else {
+    if (nf == 1) BCA_OCC2(512, 1);
+    else if (nf == 2) BCA_OCC2(512, 2);
+    else BCA_OCC2(512, 4);
+  }
+#undef BCA_OCC2
+  const int b = b1 < b2 ? b1 : b2;
+  return b < 1 ? 1 : b;
+}
+
+template <typename T>
+static int mc_occ_dispatch(int n, int C) {
+  if (C <= 4) return mc_occ<T, 4>(n);
+  if (C <= 10) return mc_occ<T, 10>(n);
+  return mc_occ<T, 16>(n);
+}
+
+int mc_occupancy_workgroups(int dtype, int n, int C) {
+  switch (dtype) {
+    case BCA_F64: return mc_occ_dispatch<double>(n, C);
+    case BCA_F32: return mc_occ_dispatch<float>(n, C);
+    default: return mc_occ_dispatch<bf16_t>(n, C);
+  }
 }
 
 template <typename T, int CC>

@@ -12,7 +12,7 @@ constexpr int PSECT = 15;  // interior points per multisection round
 template <int BT>
 __device__ double block_sum(double v, double* sh) {
   constexpr int GW = BT / 64;
-  v = wave_sum(v);
+  v = wave_sum_dpp(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wv] = v;
@@ -28,7 +28,7 @@ __device__ void block_sum_n(double (&v)[K], double* sh /* GW * K */) {
   constexpr int GW = BT / 64;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < K; ++q) v[q] = wave_sum(v[q]);
+  for (int q = 0; q < K; ++q) v[q] = wave_sum_dpp(v[q]);
   __syncthreads();
   if (lane == 0) {
 #pragma unroll

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NT) void dot_mc_kernel(StreamArgs a) {
         acc d = acc(0);
 #pragma unroll
         for (int f = 0; f < NF; ++f) d += v[r][f] * xr[f][c];
-        const double s = wave_sum((double)d);
+        const double s = wave_sum_dpp((double)d);
         if (lane == 0) red[wv][r][c] = s;
       }
     }

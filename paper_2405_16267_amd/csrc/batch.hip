@@ -155,8 +155,12 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
 #pragma unroll
         for (int e = 0; e < VEC; ++e) d += vget(v[r][q], e) * xr[q][e];
       double sv = (double)d;
-#pragma unroll
-      for (int o = LSEG / 2; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
+      if constexpr (S == 1) {
+        sv = wave_sum_dpp(sv);
+      } else {
+        sv = row16_sum_dpp(sv);                          // 16-lane segments
+        if constexpr (S == 2) sv += __shfl_xor(sv, 16, 64);  // 32-lane segments
+      }
       if (sl == r) mine = sv;
     }
     double e = 0.0;
@@ -178,7 +182,13 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
     }
     acc er[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) er[r] = (acc)__shfl(e, seg * LSEG + r, 64);
+    for (int r = 0; r < R; ++r) {
+      if constexpr (S == 1)
+        er[r] = (acc)__hiloint2double(__builtin_amdgcn_readlane(__double2hiint(e), r),
+                                      __builtin_amdgcn_readlane(__double2loint(e), r));
+      else
+        er[r] = (acc)__shfl(e, seg * LSEG + r, 64);
+    }
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
@@ -338,7 +348,7 @@ __device__ __noinline__ void trmv_item(const BatchInst& I, int part, int blk, in
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const double tot = wave_sum((s[g][0] + s[g][1]) + (s[g][2] + s[g][3]));
+      const double tot = wave_sum_dpp((s[g][0] + s[g][1]) + (s[g][2] + s[g][3]));
       const int r = r0 + g;
       if (lane == 0 && r < hi) {
         const int64_t o = (int64_t)part * I.n + c0 + r;

@@ -180,20 +180,28 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs a) {
 // holds the panels row-major, exactly as in HBM (16-byte stores, no transpose);
 // since G = sum_k a_k a_k^T may take its rows in any order, the 8 contraction
 // rows of lane group g = lane / 16 in a BF16 MFMA are rows g, g + 4, ..., g + 28
-// of the 32-row step, gathered with 2-byte LDS reads (column lane % 16).  Row
-// padding of 16 elements puts the four groups' reads in distinct banks.
+// of the 32-row step.  The four 16 x 16 subtiles of a wavefront's 64 columns are
+// interleaved (subtile x holds columns 4 i + x), so a lane reads its four
+// operands' columns at once: 8-byte reads of 4 columns per row (BF16), one
+// 16-byte read (FP32).
 template <typename T>
 struct Gram2;
 template <>
 struct Gram2<float> {
   using lds_t = float;
   using vec_t = float4;
+  using op_t = float;
   static constexpr int KB = 32;         // rows per chunk
   static constexpr int K_STEP = 4;      // contraction rows per MFMA
   static constexpr int EPV = 4;         // elements per 16-byte load
-  // operand of lane group g, column c, of the K_STEP-row step at row ks
-  __device__ static float operand(const float* p, int ks, int g, int c, int ls) {
-    return p[(ks + g) * ls + c];
+  // operands of the four interleaved subtiles (columns c4 + x, x = 0..3) for
+  // lane group g of the K_STEP-row step at row ks: one 16-byte LDS read
+  __device__ static void operands4(const float* p, int ks, int g, int c4, int ls, float (&op)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p + (ks + g) * ls + c4);
+    op[0] = v.x;
+    op[1] = v.y;
+    op[2] = v.z;
+    op[3] = v.w;
   }
   __device__ static void mma(floatx4& acc, float a, float b) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
@@ -203,14 +211,28 @@ template <>
 struct Gram2<bf16_t> {
   using lds_t = uint16_t;
   using vec_t = uint4;
+  using op_t = bf16x8;
   static constexpr int KB = 64;
   static constexpr int K_STEP = 32;
   static constexpr int EPV = 8;
-  __device__ static bf16x8 operand(const uint16_t* p, int ks, int g, int c, int ls) {
-    bf16x8 v;
+  // rows ks + g + 4 e (e = 0..7) of columns c4 .. c4 + 3: eight 8-byte LDS reads,
+  // then byte permutes put column x of rows (2p, 2p + 1) in dword p of operand x
+  __device__ static void operands4(const uint16_t* p, int ks, int g, int c4, int ls, bf16x8 (&op)[4]) {
+    uint2 r[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, p[(ks + g + 4 * e) * ls + c]);
-    return v;
+    for (int e = 0; e < 8; ++e) r[e] = *reinterpret_cast<const uint2*>(p + (ks + g + 4 * e) * ls + c4);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      uint32_t w[4];
+      const uint32_t sel = (x & 1) ? 0x07060302u : 0x05040100u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t lo = (x < 2) ? r[2 * q].x : r[2 * q].y;
+        const uint32_t hi = (x < 2) ? r[2 * q + 1].x : r[2 * q + 1].y;
+        w[q] = __builtin_amdgcn_perm(hi, lo, sel);
+      }
+      __builtin_memcpy(&op[x], w, sizeof(w));
+    }
   }
   __device__ static void mma(floatx4& acc, const bf16x8& a, const bf16x8& b) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
@@ -318,11 +340,11 @@ __global__ __launch_bounds__(256) void gram128_kernel(GramArgs a) {
     const L* pJ = diag ? lds[buf][0] : lds[buf][1];
 #pragma unroll
     for (int ks = 0; ks < KB; ks += G::K_STEP) {
-      decltype(G::operand(pI, 0, 0, 0, LS)) opa[4], opb[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) opa[x] = G::operand(pI, ks, g, wr * 64 + x * 16 + cl, LS);
-#pragma unroll
-      for (int y = 0; y < 4; ++y) opb[y] = G::operand(pJ, ks, g, wc * 64 + y * 16 + cl, LS);
+      // subtile x of a wavefront's 64 columns holds columns 4 i + x (i = 0..15),
+      // so one lane's four operands are four adjacent LDS columns
+      typename G::op_t opa[4], opb[4];
+      G::operands4(pI, ks, g, wr * 64 + 4 * cl, LS, opa);
+      G::operands4(pJ, ks, g, wc * 64 + 4 * cl, LS, opb);
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -338,8 +360,8 @@ __global__ __launch_bounds__(256) void gram128_kernel(GramArgs a) {
     for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = ti * 128 + wr * 64 + x * 16 + 4 * (lane >> 4) + v;
-        const int col = tj * 128 + wc * 64 + y * 16 + (lane & 15);
+        const int row = ti * 128 + wr * 64 + 4 * (4 * (lane >> 4) + v) + x;
+        const int col = tj * 128 + wc * 64 + 4 * (lane & 15) + y;
         if (row < nj && col < nj && row >= col) {
           const double gv = (double)acc[x][y][v];
           K[(int64_t)row * nj + col] = a.rho_l * gv + (row == col ? a.shift : 0.0);

@@ -107,3 +107,20 @@ def test_softmax_labels_in_range():
     for y in w.b:
         assert y.dtype == np.int32 and y.min() >= 0 and y.max() < 4
     assert np.count_nonzero(np.abs(w.x_true).sum(axis=1)) == 3
+
+
+def test_gaussian_block_matches_the_fp64_recipe():
+    # the fused generator draws the same normals as normal_matrix, rounds them
+    # once to FP32 (and RNE from there to BF16); with normalisation the columns
+    # have unit FP64 norm before rounding
+    m, n = 300, 37
+    supp, val = datagen.linear_model(9, n, 4)
+    (A32, Abf), b = datagen.linear_partition(9, 2, m, n, supp, val, 0.05, "f32+bf16", False)
+    G = datagen.normal_matrix(9, datagen.S_A + 2, m, n)
+    np.testing.assert_array_equal(A32, G.astype(np.float32))
+    np.testing.assert_array_equal(Abf, datagen.f32_to_bf16_bits(A32))
+    (N32, Nbf), _ = datagen.linear_partition(9, 2, m, n, supp, val, 0.05, "f32+bf16", True)
+    scale = 1.0 / np.linalg.norm(G, axis=0)
+    np.testing.assert_allclose(N32.astype(np.float64), G * scale, rtol=1e-6, atol=1e-8)
+    assert np.allclose(np.linalg.norm(N32.astype(np.float64), axis=0), 1.0, atol=1e-6)
+    np.testing.assert_array_equal(Nbf, datagen.f32_to_bf16_bits(N32))

@@ -524,95 +524,156 @@ hipError_t launch_cholesky(const FactorArgs& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ inverse factor
-// Workgroup (block, kc) computes columns [64 kc, 64 kc + 64) of W = L^-1:
-//   W[ib, kc] = L[ib, ib]^-1 (delta(ib, kc) I - sum_{kc <= pb < ib} L[ib, pb] W[pb, kc]).
-__global__ __launch_bounds__(256) void inverse_kernel(FactorArgs a) {
-  // LDS: the GEMM chunks (S0: 64 x 17, S1: 16 x 64) and the diagonal block of L
-  // (64 x 64) share one buffer; Tt holds the 64 x 64 tile being solved.
-  __shared__ double smem[64 * 64];
-  __shared__ double Tt[64 * 64];
-  double* S0 = smem;            // [64][17]
-  double* S1 = smem + 64 * 17;  // [16][64]
-  double* Ld = smem;            // [64][64]
-  const int bid = blockIdx.x;
-  const int blk = bid % a.M;
-  const int n = a.col_off[blk + 1] - a.col_off[blk];
-  const int kc = blockIdx.y;
-  if (kc * 64 >= n) return;
-  const double* L = a.kbuf + a.kmat_off[bid];
-  double* W = a.wbuf + a.kmat_off[bid];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const int nb = (n + 63) / 64;
-  const int c0 = kc * 64;
+// W = L^-1 by 64 x 64 blocks, right-looking over the block rows pb of W, all
+// N M blocks at once:
+//   inv_diag    W[b, b] = L[b, b]^-1 for every diagonal block (forward substitution,
+//               one thread per column);
+//   then for pb = 0, 1, ...:
+//   inv_row     W[pb, kc] = -W[pb, pb] S[pb, kc] for kc < pb, where S[pb, kc] =
+//               sum_{kc <= q < pb} L[pb, q] W[q, kc] has been accumulated in place;
+//   inv_update  S[ib, kc] += L[ib, pb] W[pb, kc] for ib > pb, kc <= pb.
+// Every launch works on independent 64 x 64 tiles, so the whole GPU takes part.
+constexpr int IB = 64;
 
-  for (int ib = kc; ib < nb; ++ib) {
-    const int R0 = ib * 64;
-    double acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    // sum over p in [c0, R0) of L[R0 + r, p] W[p, c0 + c]
-    for (int p0 = c0; p0 < R0; p0 += 16) {
-      for (int idx = tid; idx < 64 * 16; idx += 256) {
-        const int r = idx >> 4, p = idx & 15;
-        const int gr = R0 + r, gp = p0 + p;
-        S0[r * 17 + p] = (gr < n && gp < R0) ? L[(int64_t)gr * n + gp] : 0.0;
-      }
-      for (int idx = tid; idx < 16 * 64; idx += 256) {
-        const int p = idx >> 6, c = idx & 63;
-        const int gp = p0 + p, gc = c0 + c;
-        S1[p * 64 + c] = (gp < R0 && gc < n) ? W[(int64_t)gp * n + gc] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int p = 0; p < 16; ++p) {
-        double li[4], wj[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) li[x] = S0[(ty + 16 * x) * 17 + p];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) wj[y] = S1[p * 64 + tx + 16 * y];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * wj[y];
-      }
-      __syncthreads();
+__device__ __forceinline__ void inv_matrix(const FactorArgs& a, int bid, int* n, const double** L, double** W) {
+  const int blk = bid % a.M;
+  *n = a.col_off[blk + 1] - a.col_off[blk];
+  *L = a.kbuf + a.kmat_off[bid];
+  *W = a.wbuf + a.kmat_off[bid];
+}
+
+__global__ __launch_bounds__(256) void inv_diag_kernel(FactorArgs a) {
+  __shared__ double Ld[IB][IB + 1];
+  __shared__ double X[IB][IB + 1];
+  int n;
+  const double* L;
+  double* W;
+  inv_matrix(a, blockIdx.y, &n, &L, &W);
+  const int R0 = blockIdx.x * IB;
+  if (R0 >= n) return;
+  const int nr = min(IB, n - R0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < IB * IB; idx += 256) {
+    const int r = idx / IB, q = idx % IB;
+    Ld[r][q] = (r < nr && q <= r) ? L[(int64_t)(R0 + r) * n + R0 + q] : (q == r ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (tid < IB) {
+    const int c = tid;
+    for (int r = 0; r < IB; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int q = c; q < r; ++q) v -= Ld[r][q] * X[q][c];
+      X[r][c] = r < c ? 0.0 : v / Ld[r][r];
     }
-    // right-hand side tile: delta I - acc; diagonal block of L into LDS
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int r = ty + 16 * x, c = tx + 16 * y;
-        Tt[r * 64 + c] = ((ib == kc && r == c) ? 1.0 : 0.0) - acc[x][y];
-      }
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-      const int r = idx >> 6, q = idx & 63;
-      Ld[idx] = (R0 + r < n && q <= r) ? L[(int64_t)(R0 + r) * n + R0 + q] : (q == r ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    // forward substitution with L[ib, ib], one thread per column
-    if (tid < 64) {
-      const int c = tid;
-      for (int r = 0; r < 64; ++r) {
-        double v = Tt[r * 64 + c];
-        for (int q = 0; q < r; ++q) v -= Ld[r * 64 + q] * Tt[q * 64 + c];
-        Tt[r * 64 + c] = v / Ld[r * 64 + r];
-      }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-      const int r = idx >> 6, c = idx & 63;
-      if (R0 + r < n && c0 + c < n) W[(int64_t)(R0 + r) * n + c0 + c] = Tt[idx];
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int idx = tid; idx < IB * IB; idx += 256) {
+    const int r = idx / IB, c = idx % IB;
+    if (r < nr && c <= r) W[(int64_t)(R0 + r) * n + R0 + c] = X[r][c];
   }
 }
 
+__global__ __launch_bounds__(256) void inv_row_kernel(FactorArgs a, int pb) {
+  __shared__ double D[IB][IB + 1];
+  __shared__ double Sm[IB][IB + 1];
+  int n;
+  const double* L;
+  double* W;
+  inv_matrix(a, blockIdx.y, &n, &L, &W);
+  const int R0 = pb * IB;
+  const int kc = blockIdx.x;
+  if (R0 >= n || kc >= pb) return;
+  const int nr = min(IB, n - R0);
+  const int C0 = kc * IB;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int idx = tid; idx < IB * IB; idx += 256) {
+    const int r = idx / IB, q = idx % IB;
+    D[r][q] = (r < nr && q <= r) ? W[(int64_t)(R0 + r) * n + R0 + q] : 0.0;
+    Sm[r][q] = r < nr ? W[(int64_t)(R0 + r) * n + C0 + q] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int q = 0; q < IB; ++q) {
+    double dv[4], sv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) dv[x] = D[ty + 16 * x][q];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) sv[y] = Sm[q][tx + 16 * y];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += dv[x] * sv[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = ty + 16 * x, c = tx + 16 * y;
+      if (r < nr) W[(int64_t)(R0 + r) * n + C0 + c] = -acc[x][y];
+    }
+}
+
+__global__ __launch_bounds__(256) void inv_update_kernel(FactorArgs a, int pb) {
+  __shared__ double Lt[IB][IB + 1];
+  __shared__ double Wt[IB][IB + 1];
+  int n;
+  const double* L;
+  double* W;
+  inv_matrix(a, blockIdx.y, &n, &L, &W);
+  const int nb = (n + IB - 1) / IB;
+  const int ib = pb + 1 + blockIdx.x / (pb + 1);
+  const int kc = blockIdx.x % (pb + 1);
+  if (ib >= nb) return;
+  const int R0 = ib * IB, P0 = pb * IB, C0 = kc * IB;
+  const int nr = min(IB, n - R0);
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int idx = tid; idx < IB * IB; idx += 256) {
+    const int r = idx / IB, q = idx % IB;
+    Lt[r][q] = r < nr ? L[(int64_t)(R0 + r) * n + P0 + q] : 0.0;
+    Wt[r][q] = (kc < pb || q <= r) ? W[(int64_t)(P0 + r) * n + C0 + q] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = ty + 16 * x, c = tx + 16 * y;
+      acc[x][y] = r < nr ? W[(int64_t)(R0 + r) * n + C0 + c] : 0.0;
+    }
+  for (int q = 0; q < IB; ++q) {
+    double lv[4], wv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) lv[x] = Lt[ty + 16 * x][q];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) wv[y] = Wt[q][tx + 16 * y];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += lv[x] * wv[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = ty + 16 * x, c = tx + 16 * y;
+      if (r < nr) W[(int64_t)(R0 + r) * n + C0 + c] = acc[x][y];
+    }
+}
+
 hipError_t launch_inverse(const FactorArgs& a, hipStream_t s) {
-  dim3 grid(a.N * a.M, (a.nj_max + 63) / 64);
-  hipLaunchKernelGGL(inverse_kernel, grid, dim3(256), 0, s, a);
+  const int nm = a.N * a.M;
+  const int nb = (a.nj_max + IB - 1) / IB;
+  hipLaunchKernelGGL(inv_diag_kernel, dim3(nb, nm), dim3(256), 0, s, a);
+  for (int pb = 0; pb < nb; ++pb) {
+    if (pb > 0) hipLaunchKernelGGL(inv_row_kernel, dim3(pb, nm), dim3(256), 0, s, a, pb);
+    const int rest = nb - pb - 1;
+    if (rest > 0) hipLaunchKernelGGL(inv_update_kernel, dim3(rest * (pb + 1), nm), dim3(256), 0, s, a, pb);
+  }
   return hipGetLastError();
 }
 

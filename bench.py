@@ -165,7 +165,7 @@ def batched_bench(args):
     for w in ws:
         for j in range(w.n_blocks):
             nj = w.n // w.n_blocks + (1 if j < w.n % w.n_blocks else 0)
-            fac_bytes += w.N * nj * (nj + 1) * 8
+            fac_bytes += w.N * nj * (nj + 1) // 2 * 8   # distinct entries of K_ij^-1
     inner = args.iters * ws[0].inner_iters
     gbps = (a_bytes + fac_bytes) * inner / el / 1e9
     its = [P.residuals()[3] for P in probs]
@@ -192,7 +192,7 @@ def precision_bench(args):
     from.  Both forms run the same iterations; reported: iter/s and the streaming
     roofline of each, the Gram's MFMA utilisation for each dtype, and the BF16
     result's deviation from the FP32 result with the first-order BF16 bound
-    4 cond(K) 2^-8 (cond of feature block 0 of partition 0, from its factor)."""
+    4 cond(K) 2^-8 (cond of feature block 0 of partition 0, from its cached inverse)."""
     import numpy as np
     import torch
     import datagen
@@ -252,9 +252,8 @@ def precision_bench(args):
     xb, x32 = Pb.coef(), P32.coef()
     fb, f32 = Pb.objective(), P32.objective()
     same_support = bool(np.array_equal(Pb.support(), P32.support()))
-    W = P32.factor(0, 0)
-    sv = np.linalg.svd(W, compute_uv=False)
-    condK = float((sv[0] / sv[-1]) ** 2)
+    ev = np.linalg.eigvalsh(P32.inverse(0, 0))
+    condK = float(ev[-1] / ev[0])
     Pb.close()
     P32.close()
     err = float(np.linalg.norm(xb - x32) / np.linalg.norm(x32))
@@ -464,8 +463,8 @@ def main():
     stream_avg_s = st_ms / max(n_st, 1) / 1e3
     achieved = stream_bytes / stream_avg_s / 1e9
     bounds = [(w.n // w.n_blocks + (1 if j < w.n % w.n_blocks else 0)) for j in range(w.n_blocks)]
-    # factor bytes of one block solve: both packed triangles of W_ij = L_ij^-1 (FP64)
-    factor_bytes = w.N * sum(nj * (nj + 1) * 8 for nj in bounds)
+    # bytes of one block solve: the distinct entries of the symmetric K_ij^-1 (FP64)
+    factor_bytes = w.N * sum(nj * (nj + 1) // 2 * 8 for nj in bounds)
     inner_bytes = stream_bytes + factor_bytes
     ms_per_step = elapsed / args.steps * 1e3
     src_hash = source_hash(STREAM_SOURCES)

@@ -170,10 +170,13 @@ int bca_set_vector(bca_problem p, int32_t which, int32_t part, const double* in)
 int bca_get_state(bca_problem p, void* buf, size_t* bytes);
 int bca_set_state(bca_problem p, const void* buf, size_t bytes);
 
-/* The inverse Cholesky factor W_ij = L_ij^-1 of block (part, block), written
- * dense row-major n_j x n_j (upper part zero) to host memory.  For tests of the
- * setup: W^T W = K_ij^-1. */
-int bca_get_factor(bca_problem p, int32_t part, int32_t block, double* W);
+/* The cached inverse P_ij = K_ij^-1 of block (part, block) (Sec. 3.1: the
+ * matrix of the x_ij-step's regularised least-squares problem, K_ij =
+ * rho_l A_ij^T A_ij + (1/(N gamma) + rho_c) I), written dense row-major
+ * n_j x n_j to host memory owned by the caller.  It is formed once at finalize
+ * in FP64 from the Cholesky factor: P_ij = W_ij^T W_ij with W_ij = L_ij^-1.
+ * For tests of the setup: P_ij K_ij = I. */
+int bca_get_inverse(bca_problem p, int32_t part, int32_t block, double* Kinv);
 
 /* Kernel timing with HIP events on the problem's stream (off by default).
  * Classes: 0 = A-streaming pass (block matvecs, prox, duals), 1 = block

@@ -27,7 +27,7 @@ KC_STREAM, KC_SOLVE, KC_GLOBAL, KC_GRAM, KC_FACTOR = range(5)
 EXPORTS = ["bca_create", "bca_set_data", "bca_finalize", "bca_step", "bca_solve",
            "bca_get_support", "bca_get_coef", "bca_get_residuals", "bca_get_history",
            "bca_get_objective", "bca_get_vector", "bca_set_vector", "bca_get_state",
-           "bca_set_state", "bca_get_factor", "bca_set_timing", "bca_get_timing", "bca_destroy",
+           "bca_set_state", "bca_get_inverse", "bca_set_timing", "bca_get_timing", "bca_destroy",
            "bca_last_error", "bca_topk", "bca_batch_step", "bca_batch_solve",
            "bca_batch_autotune", "bca_batch_set_shape", "bca_batch_get_shape",
            "bca_server_create", "bca_server_submit", "bca_server_poll", "bca_server_fetch",
@@ -75,7 +75,7 @@ def _load():
         "bca_set_vector": [P, i32, i32, P],
         "bca_get_state": [P, P, psz],
         "bca_set_state": [P, P, ctypes.c_size_t],
-        "bca_get_factor": [P, i32, i32, P],
+        "bca_get_inverse": [P, i32, i32, P],
         "bca_set_timing": [P, i32],
         "bca_get_timing": [P, i32, pi32, pdbl],
         "bca_destroy": [P],
@@ -268,12 +268,13 @@ class Problem:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.bca_set_state(self._h, buf, len(blob)))
 
-    def factor(self, part: int, block: int) -> np.ndarray:
+    def inverse(self, part: int, block: int) -> np.ndarray:
+        """The cached K_ij^-1 of block (part, block), dense n_j x n_j."""
         q, r = divmod(self.n, self.M)
         nj = q + (1 if block < r else 0)
-        W = np.zeros((nj, nj))
-        _check(_lib.bca_get_factor(self._h, part, block, _ptr(W)))
-        return W
+        K = np.zeros((nj, nj))
+        _check(_lib.bca_get_inverse(self._h, part, block, _ptr(K)))
+        return K
 
     def batch_shape(self):
         t, i = ctypes.c_int32(), ctypes.c_int32()

@@ -30,7 +30,7 @@ FLAGS = [
 
 def _inputs():
     deps = [os.path.join(CSRC, s) for s in SOURCES]
-    deps += [os.path.join(CSRC, h) for h in ("bca_internal.h", "global_impl.h", "prox_impl.h")]
+    deps += [os.path.join(CSRC, h) for h in ("bca_internal.h", "global_impl.h", "prox_impl.h", "symv_impl.h")]
     deps += [os.path.join(INCLUDE, "bca.h")]
     return deps
 

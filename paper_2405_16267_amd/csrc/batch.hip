@@ -7,9 +7,12 @@
 // spanning all problems:
 //   RHS     item (problem, partition, block): the FP64 reduction of that block's
 //           A^T e partial sums into the right-hand side of the x_ij-step;
-//   TRMV0/1 item (problem, partition, block, row range): the two triangular
-//           products with the cached inverse factor, y = W r then x += W^T y,
-//           each a phase of its own so a large block is shared by many workgroups;
+//   SYMV    item (problem, partition, block, tile range): one wavefront applies
+//           tiles of the cached inverse P_ij = K_ij^-1 to r (symmetric product,
+//           each stored tile read once), so a large block is shared by many
+//           wavefronts;
+//   XUPD    item (problem, partition, block): x += P_ij r from the product's
+//           slots, in a fixed order, and the streaming copy of x;
 //   STREAM  item (problem, partition, row chunk): the fused streaming pass over
 //           a chunk of rows by one wavefront (block predictions, sample-space
 //           average, omega-bar prox, nu update, e, partial A^T e of the chunk);
@@ -32,6 +35,7 @@
 #include "bca_internal.h"
 #include "global_impl.h"
 #include "prox_impl.h"
+#include "symv_impl.h"
 
 namespace bca {
 
@@ -39,7 +43,6 @@ namespace cg = cooperative_groups;
 
 constexpr int BT = 256;
 constexpr int BW = BT / 64;
-constexpr int NJ_MAX = 1024;  // largest block width of a batched problem
 
 // Shapes (chunks per lane NC, rows per segment tile R, segments per wave S): a
 // wavefront is split into S segments of 64 / S lanes, each streaming its own rows,
@@ -256,10 +259,10 @@ __device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, in
 }
 
 // x_ij-step of one block, in three phases of independent items so that a large
-// block's factor is read by many workgroups at once:
-//   RHS   (partition, block): r = rho_l sum_w gpart_w + rho_c (z - u) - shift x;
-//   TRMV0 (partition, block, row range): y_r = sum_{c <= r} W[r][c] r_c   (packed rows);
-//   TRMV1 (partition, block, row range): x_r += sum_{c >= r} W[c][r] y_c  (packed columns).
+// block's inverse is read by many wavefronts at once:
+//   RHS  (partition, block): r = rho_l sum_w gpart_w + rho_c (z - u) - shift x;
+//   SYMV (partition, block, tile range): slots of y = P_ij r (symv_impl.h);
+//   XUPD (partition, block): x += y, y summed from the slots in a fixed order.
 __device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk) {
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
@@ -281,92 +284,40 @@ __device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk) {
   }
 }
 
-// Rows [lo, hi) of one triangular product.  A wavefront takes 4 consecutive rows
-// at once (groups lo + 4 g, g = wave, wave + 4, ...) and walks them together in
-// chunks of 256 entries per row, so 16 loads per lane are in flight; each row's
-// sum has a fixed order (4 partial sums per lane, then the wavefront reduction).
-__device__ __noinline__ void trmv_item(const BatchInst& I, int part, int blk, int lo, int hi, int tr,
-                                       double* vsh) {
-  constexpr int G = 4;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// Tiles [t0, t1) of block (part, blk), one after the other, by one wavefront.
+__device__ __noinline__ void symv_item(const BatchInst& I, int part, int blk, int t0, int t1) {
+  const int bid = part * I.M + blk;
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
-  const double* vin = (tr == 0 ? I.rhs : I.y) + (int64_t)part * I.n + c0;
-  for (int c = tid; c < nj; c += BT) vsh[c] = vin[c];
-  __syncthreads();
-  const double* F = (tr == 0 ? I.wr : I.wc) + I.fac_off[part * I.M + blk];
-  for (int r0 = lo + G * wv; r0 < hi; r0 += G * BW) {
-    const double* f[G];
-    const double* v[G];
-    int len[G];
-    int maxlen = 0;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int r = r0 + g;
-      if (r < hi) {
-        int64_t off;
-        int st;
-        if (tr == 0) {
-          off = (int64_t)r * (r + 1) / 2;
-          st = 0;
-          len[g] = r + 1;
-        } else {
-          off = (int64_t)r * nj - (int64_t)r * (r - 1) / 2;
-          st = r;
-          len[g] = nj - r;
-        }
-        f[g] = F + off;
-        v[g] = vsh + st;
-      } else {
-        f[g] = F;
-        v[g] = vsh;
-        len[g] = 0;
-      }
-      maxlen = max(maxlen, len[g]);
-    }
-    double s[G][4];
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) s[g][u] = 0.0;
-    for (int e0 = 0; e0 < maxlen; e0 += 256) {
-      double fv[G][4];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = e0 + 64 * u + lane;
-          fv[g][u] = e < len[g] ? f[g][e] : 0.0;
-        }
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = e0 + 64 * u + lane;
-          if (e < len[g]) s[g][u] += fv[g][u] * v[g][e];
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const double tot = wave_sum_dpp((s[g][0] + s[g][1]) + (s[g][2] + s[g][3]));
-      const int r = r0 + g;
-      if (lane == 0 && r < hi) {
-        const int64_t o = (int64_t)part * I.n + c0 + r;
-        if (tr == 0) {
-          I.y[o] = tot;
-        } else {
-          const double xn = I.x[o] + tot;
-          I.x[o] = xn;
-          const int64_t so = (int64_t)part * I.ld + c0 + r;
-          if (I.dtype == BCA_F64)
-            reinterpret_cast<double*>(I.xs)[so] = xn;
-          else
-            reinterpret_cast<float*>(I.xs)[so] = (float)xn;
-        }
-      }
-    }
+  const int T = (nj + PT - 1) / PT;
+  const double* P = I.kinv + I.fac_off[bid];
+  const double* r = I.rhs + (int64_t)part * I.n + c0;
+  double* ys = I.ypart + (int64_t)bid * I.tmax * I.tmax * PT;
+  for (int t = t0; t < t1; ++t) {
+    int ti, tj;
+    tri_tile(t, &ti, &tj);
+    symv_tile(P + (int64_t)t * PT_ELEMS, r, nj, 1, ti, tj, T, ys);
   }
-  __syncthreads();  // vsh is reused by the next item
+}
+
+// x += y over the block's n_j features by one wavefront.
+__device__ __noinline__ void xupd_item(const BatchInst& I, int part, int blk) {
+  const int bid = part * I.M + blk;
+  const int c0 = I.col_off[blk];
+  const int nj = I.col_off[blk + 1] - c0;
+  const int T = (nj + PT - 1) / PT;
+  const double* ys = I.ypart + (int64_t)bid * I.tmax * I.tmax * PT;
+  for (int i = threadIdx.x & 63; i < nj; i += 64) {
+    const double y = symv_gather(ys, i, 0, 1, T);
+    const int64_t o = (int64_t)part * I.n + c0 + i;
+    const double xn = I.x[o] + y;
+    I.x[o] = xn;
+    const int64_t so = (int64_t)part * I.ld + c0 + i;
+    if (I.dtype == BCA_F64)
+      reinterpret_cast<double*>(I.xs)[so] = xn;
+    else
+      reinterpret_cast<float*>(I.xs)[so] = (float)xn;
+  }
 }
 
 // Out of line, with 7 multisection points per round, so that the global step's
@@ -399,9 +350,8 @@ __device__ GlobalArgs global_args_of(const BatchInst& I) {
 
 // Two workgroups per CU: at most 256 registers per lane (VGPRs and AGPRs).
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(BatchArgs ba) {
-  // the solve phase's right-hand side and intermediate vector, and the widest
-  // stream shape's partial sums, use the same LDS (phases never overlap)
-  __shared__ double big[NJ_MAX > 32 * BT ? NJ_MAX : 32 * BT];
+  // the widest stream shape's partial sums
+  __shared__ double big[32 * BT];
   __shared__ double shd[BW * (PSECT + 2)];
   __shared__ TopkShared<BT> tks;
   __shared__ int item_sh;
@@ -416,8 +366,9 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
     __syncthreads();
     return it;
   };
-  // stream items are claimed by single wavefronts (no workgroup barrier between
-  // items, so the 8 wavefronts of a CU overlap their per-item latencies)
+  // stream and symmetric-product items are claimed by single wavefronts (no
+  // workgroup barrier between items, so the 8 wavefronts of a CU overlap their
+  // per-item latencies)
   auto claim_wave = [&]() {
     int it = 0;
     if ((threadIdx.x & 63) == 0) it = (int)atomicAdd(&ba.counters[phase], 1u);
@@ -451,16 +402,22 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
       }
       ++phase;
       grid.sync();
-      for (int tr = 0; tr < 2; ++tr) {
-        for (int it = claim(); it < ba.n_trmv[tr]; it = claim()) {
-          const BatchItem w = ba.trmv_items[tr][it];
-          const BatchInst& I = ba.inst[w.inst];
-          if (o >= I.outer || k >= I.inner_iters) continue;
-          trmv_item(I, w.a, w.b, w.c, w.d, tr, big);
-        }
-        ++phase;
-        grid.sync();
+      for (int it = claim_wave(); it < ba.n_symv; it = claim_wave()) {
+        const BatchItem w = ba.symv_items[it];
+        const BatchInst& I = ba.inst[w.inst];
+        if (o >= I.outer || k >= I.inner_iters) continue;
+        symv_item(I, w.a, w.b, w.c, w.d);
       }
+      ++phase;
+      grid.sync();
+      for (int it = claim_wave(); it < ba.n_xupd; it = claim_wave()) {
+        const BatchItem w = ba.xupd_items[it];
+        const BatchInst& I = ba.inst[w.inst];
+        if (o >= I.outer || k >= I.inner_iters) continue;
+        xupd_item(I, w.a, w.b);
+      }
+      ++phase;
+      grid.sync();
       run_stream(ba.stream_items, ba.n_stream, 0, k, o);
       grid.sync();
     }

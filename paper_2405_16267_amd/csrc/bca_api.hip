@@ -6,10 +6,12 @@
 //            [row_off[i], row_off[i+1]); block j is columns [col_off[j], col_off[j+1]);
 //            ld = n rounded up to 64 elements (columns >= n are zero and never read)
 //   b, omega-bar, nu          m_total doubles each
-//   x, u, rhs, tmp            N x n doubles;  xs: N x ld streaming copy of x
+//   x, u, rhs                 N x n doubles;  xs: N x ld streaming copy of x
 //   z, s                      n doubles;  scal: t, v, p_r, d_r, b_r, iteration
 //   gpart                     N x Gp x ld doubles (per-workgroup partial A^T e)
-//   wr, wc                    packed W_ij = L_ij^-1 (rows, columns): sum_ij n_j (n_j + 1) / 2 each
+//   kinv                      P_ij = K_ij^-1 as 64 x 64 tiles of its lower block triangle
+//                             (sum_ij T_ij (T_ij + 1) / 2 tiles, T_ij = ceil(n_j / 64))
+//   ypart                     N M x tmax x tmax x 64 doubles: slots of the symmetric product
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -73,14 +75,14 @@ struct bca_problem_s {
   int32_t* y = nullptr;
   double *omega = nullptr, *nu = nullptr;
   double* rowbuf = nullptr;   // m_total x C, multi-class pass (averages, then e)
-  double *x = nullptr, *u = nullptr, *rhs = nullptr, *tmp = nullptr;
+  double *x = nullptr, *u = nullptr, *rhs = nullptr, *ypart = nullptr;
   void* xs = nullptr;
   void* xhat_s = nullptr;
   double *z = nullptr, *s = nullptr, *scal = nullptr, *hist = nullptr, *work = nullptr;
   int32_t* support = nullptr;
   int* status = nullptr;
   double* gpart = nullptr;
-  double *wr = nullptr, *wc = nullptr;
+  double* kinv = nullptr;
   double* objpart = nullptr;
   int64_t* d_row_off = nullptr;
   int32_t* d_col_off = nullptr;
@@ -245,9 +247,8 @@ SolveArgs solve_args(bca_problem P) {
   a.u = P->u;
   a.z = P->z;
   a.rhs = P->rhs;
-  a.tmp = P->tmp;
-  a.wr = P->wr;
-  a.wc = P->wc;
+  a.ypart = P->ypart;
+  a.kinv = P->kinv;
   a.fac_off = P->d_fac_off;
   a.col_off = P->d_col_off;
   a.N = P->N;
@@ -382,7 +383,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
       P->nj_max = std::max<int>(P->nj_max, (int)nj);
       P->fac_off[(size_t)i * P->M + j] = fo;
       P->kmat_off[(size_t)i * P->M + j] = ko;
-      fo += nj * (nj + 1) / 2;
+      fo += ptile_count((int)nj) * PT_ELEMS;
       ko += nj * nj;
     }
   P->fac_total = fo;
@@ -432,7 +433,10 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->x, (size_t)P->N * P->n * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->u, (size_t)P->N * P->n * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->rhs, (size_t)P->N * P->n * C));
-  if (rc == BCA_OK) chk(dalloc(P, &P->tmp, (size_t)P->N * P->n * C));
+  if (rc == BCA_OK) {
+    const int64_t tm = (P->nj_max + PT - 1) / PT;
+    chk(dalloc(P, &P->ypart, (size_t)(P->N * P->M) * tm * tm * PT * C));
+  }
   if (rc == BCA_OK) {
     void* q = nullptr;
     hipError_t e = hipMalloc(&q, (size_t)P->N * P->ld * C * (xs_is_f64(P) ? 8 : 4));
@@ -450,8 +454,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->support, (size_t)P->kappa));
   if (rc == BCA_OK) chk(dalloc(P, &P->status, 4));
   if (rc == BCA_OK) chk(dalloc(P, &P->gpart, (size_t)P->N * P->Gp * P->ld * C));
-  if (rc == BCA_OK) chk(dalloc(P, &P->wr, (size_t)P->fac_total));
-  if (rc == BCA_OK) chk(dalloc(P, &P->wc, (size_t)P->fac_total));
+  if (rc == BCA_OK) chk(dalloc(P, &P->kinv, (size_t)P->fac_total));
   if (rc == BCA_OK) chk(dalloc(P, &P->objpart, (size_t)P->N * P->Gp));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_row_off, P->N + 1));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_col_off, P->M + 1));
@@ -559,8 +562,7 @@ int bca_finalize(bca_problem P) {
   f.wbuf = wbuf;
   f.kmat_off = P->d_kmat_off;
   f.col_off = P->d_col_off;
-  f.wr = P->wr;
-  f.wc = P->wc;
+  f.kinv = P->kinv;
   f.fac_off = P->d_fac_off;
   f.status = P->status;
   f.N = P->N;
@@ -574,7 +576,7 @@ int bca_finalize(bca_problem P) {
     Timer t(P, BCA_KC_FACTOR);
     e = launch_cholesky(f, s);
     if (e == hipSuccess) e = launch_inverse(f, s);
-    if (e == hipSuccess) e = launch_pack(f, s);
+    if (e == hipSuccess) e = launch_kinv(f, s);
   }
   // zero ADMM state (all-zero start); A^T e = 0 for it
   const size_t nx = (size_t)P->N * P->n * P->C;
@@ -855,17 +857,28 @@ int bca_set_state(bca_problem P, const void* buf, size_t bytes) {
   return BCA_OK;
 }
 
-int bca_get_factor(bca_problem P, int32_t part, int32_t block, double* W) {
-  if (!P || !W) return fail(BCA_E_INVALID, "null argument");
-  if (!P->finalized) return fail(BCA_E_STATE, "no factor before finalize");
+int bca_get_inverse(bca_problem P, int32_t part, int32_t block, double* Kinv) {
+  if (!P || !Kinv) return fail(BCA_E_INVALID, "null argument");
+  if (!P->finalized) return fail(BCA_E_STATE, "no inverse before finalize");
   if (part < 0 || part >= P->N || block < 0 || block >= P->M) return fail(BCA_E_INVALID, "index out of range");
-  const int64_t nj = P->col_off[block + 1] - P->col_off[block];
-  std::vector<double> pk((size_t)(nj * (nj + 1) / 2));
-  HIP_TRY(hipMemcpyAsync(pk.data(), P->wr + P->fac_off[(size_t)part * P->M + block], pk.size() * 8,
+  const int nj = P->col_off[block + 1] - P->col_off[block];
+  const int T = (nj + PT - 1) / PT;
+  std::vector<double> tiles((size_t)ptile_count(nj) * PT_ELEMS);
+  HIP_TRY(hipMemcpyAsync(tiles.data(), P->kinv + P->fac_off[(size_t)part * P->M + block], tiles.size() * 8,
                          hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
-  for (int64_t r = 0; r < nj; ++r)
-    for (int64_t c = 0; c < nj; ++c) W[r * nj + c] = c <= r ? pk[(size_t)(r * (r + 1) / 2 + c)] : 0.0;
+  for (int I = 0; I < T; ++I)
+    for (int J = 0; J <= I; ++J) {
+      const double* t = tiles.data() + (size_t)(I * (I + 1) / 2 + J) * PT_ELEMS;
+      for (int r = 0; r < PT; ++r)
+        for (int c = 0; c < PT; ++c) {
+          const int gr = I * PT + r, gc = J * PT + c;
+          if (gr >= nj || gc >= nj) continue;
+          const double v = t[ptile_pos(r, c)];
+          Kinv[(int64_t)gr * nj + gc] = v;
+          if (I != J) Kinv[(int64_t)gc * nj + gr] = v;
+        }
+    }
   return BCA_OK;
 }
 
@@ -985,9 +998,8 @@ BatchInst batch_desc(bca_problem P, int outer) {
   I.status = P->status;
   I.gpart = P->bgpart;
   I.rhs = P->rhs;
-  I.y = P->tmp;
-  I.wr = P->wr;
-  I.wc = P->wc;
+  I.ypart = P->ypart;
+  I.kinv = P->kinv;
   I.fac_off = P->d_fac_off;
   I.col_off = P->d_col_off;
   I.N = P->N;
@@ -999,6 +1011,7 @@ BatchInst batch_desc(bca_problem P, int outer) {
   I.nvec = P->nvec;
   I.hist_cap = P->p.max_iters;
   I.inner_iters = P->p.inner_iters;
+  I.tmax = (P->nj_max + PT - 1) / PT;
   I.rows_per_item = batch_rows_item(P);
   I.items_per_part = (int)batch_items_per_part(P);
   I.shape = batch_shape_code(P->nvec, batch_rows_tile(P));
@@ -1017,12 +1030,11 @@ BatchInst batch_desc(bca_problem P, int outer) {
 int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, hipStream_t s,
                  bool stream_only, float* ms) {
   std::vector<BatchInst> desc(count);
-  std::vector<BatchItem> solve, stream, primei, trmv[2];
+  std::vector<BatchItem> solve, stream, primei, symv, xupd;
   int outer_max = 0, inner_max = 0;
-  // Row ranges of the triangular products: about kTrmvWork factor entries per
-  // item (row r of W has r + 1 entries, column r has n_j - r), fixed by n_j alone
-  // so a problem is split the same way in every batch.
-  constexpr int64_t kTrmvWork = 32768;
+  // Tile ranges of the symmetric products: kSymvTiles tiles of P_ij per item,
+  // fixed by n_j alone so a problem is split the same way in every batch.
+  constexpr int kSymvTiles = 8;
   for (int r = 0; r < count; ++r) {
     bca_problem P = probs[r];
     TRY(batch_ensure_partials(P));
@@ -1033,19 +1045,9 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     for (int i = 0; i < P->N; ++i) {
       for (int j = 0; j < P->M; ++j) {
         solve.push_back({r, i, j, 0, 0});
-        const int nj = P->col_off[j + 1] - P->col_off[j];
-        for (int tr = 0; tr < 2; ++tr) {
-          int lo = 0;
-          int64_t acc = 0;
-          for (int row = 0; row < nj; ++row) {
-            acc += tr == 0 ? row + 1 : nj - row;
-            if (acc >= kTrmvWork || row == nj - 1) {
-              trmv[tr].push_back({r, i, j, lo, row + 1});
-              lo = row + 1;
-              acc = 0;
-            }
-          }
-        }
+        xupd.push_back({r, i, j, 0, 0});
+        const int nt = (int)ptile_count(P->col_off[j + 1] - P->col_off[j]);
+        for (int t0 = 0; t0 < nt; t0 += kSymvTiles) symv.push_back({r, i, j, t0, std::min(nt, t0 + kSymvTiles)});
       }
       for (int c = 0; c < ipp; ++c) {
         stream.push_back({r, i, c, 0, 0});
@@ -1053,33 +1055,24 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
       }
     }
   }
-  // largest work first: rhs items by n_j x partials, triangular items by
-  // entries, stream items by rows x vectors
+  // largest work first: rhs and update items by n_j (x partials), product items
+  // by tiles, stream items by rows x vectors
   auto solve_cost = [&](const BatchItem& w) {
     bca_problem P = probs[w.inst];
     const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
     return nj * batch_items_per_part(P);
   };
-  auto trmv_cost = [&](int tr) {
-    return [&, tr](const BatchItem& w) {
-      bca_problem P = probs[w.inst];
-      const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
-      int64_t c = 0;
-      for (int64_t row = w.c; row < w.d; ++row) c += tr == 0 ? row + 1 : nj - row;
-      return c;
-    };
+  auto xupd_cost = [&](const BatchItem& w) {
+    bca_problem P = probs[w.inst];
+    const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
+    return nj * ((nj + PT - 1) / PT);
   };
-  for (int tr = 0; tr < 2; ++tr) {
-    auto cost = trmv_cost(tr);
-    std::vector<std::pair<int64_t, BatchItem>> keyed;
-    keyed.reserve(trmv[tr].size());
-    for (const auto& w : trmv[tr]) keyed.push_back({cost(w), w});
-    std::stable_sort(keyed.begin(), keyed.end(),
-                     [](const std::pair<int64_t, BatchItem>& a, const std::pair<int64_t, BatchItem>& b) {
-                       return a.first > b.first;
-                     });
-    for (size_t q = 0; q < keyed.size(); ++q) trmv[tr][q] = keyed[q].second;
-  }
+  std::stable_sort(symv.begin(), symv.end(), [](const BatchItem& a, const BatchItem& b) {
+    return a.d - a.c > b.d - b.c;
+  });
+  std::stable_sort(xupd.begin(), xupd.end(), [&](const BatchItem& a, const BatchItem& b) {
+    return xupd_cost(a) > xupd_cost(b);
+  });
   auto stream_cost = [&](const BatchItem& w) {
     bca_problem P = probs[w.inst];
     const int64_t lo = (int64_t)w.b * batch_rows_item(P);
@@ -1100,9 +1093,9 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t off_desc = 0;
   const size_t off_solve = off_desc + al(desc.size() * sizeof(BatchInst));
-  const size_t off_t0 = off_solve + al(solve.size() * sizeof(BatchItem));
-  const size_t off_t1 = off_t0 + al(trmv[0].size() * sizeof(BatchItem));
-  const size_t off_stream = off_t1 + al(trmv[1].size() * sizeof(BatchItem));
+  const size_t off_symv = off_solve + al(solve.size() * sizeof(BatchItem));
+  const size_t off_xupd = off_symv + al(symv.size() * sizeof(BatchItem));
+  const size_t off_stream = off_xupd + al(xupd.size() * sizeof(BatchItem));
   const size_t off_prime = off_stream + al(stream.size() * sizeof(BatchItem));
   const size_t off_cnt = off_prime + al(primei.size() * sizeof(BatchItem));
   const size_t total = off_cnt + al((size_t)std::max(phases, 1) * sizeof(unsigned int));
@@ -1117,10 +1110,10 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   HIP_TRY(hipMemcpyAsync(base + off_desc, desc.data(), desc.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s));
   if (!solve.empty())
     HIP_TRY(hipMemcpyAsync(base + off_solve, solve.data(), solve.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
-  if (!trmv[0].empty())
-    HIP_TRY(hipMemcpyAsync(base + off_t0, trmv[0].data(), trmv[0].size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
-  if (!trmv[1].empty())
-    HIP_TRY(hipMemcpyAsync(base + off_t1, trmv[1].data(), trmv[1].size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  if (!symv.empty())
+    HIP_TRY(hipMemcpyAsync(base + off_symv, symv.data(), symv.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+  if (!xupd.empty())
+    HIP_TRY(hipMemcpyAsync(base + off_xupd, xupd.data(), xupd.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   if (!stream.empty())
     HIP_TRY(hipMemcpyAsync(base + off_stream, stream.data(), stream.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   if (!primei.empty())
@@ -1131,10 +1124,10 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   a.count = count;
   a.rhs_items = reinterpret_cast<const BatchItem*>(base + off_solve);
   a.n_rhs = (int)solve.size();
-  a.trmv_items[0] = reinterpret_cast<const BatchItem*>(base + off_t0);
-  a.trmv_items[1] = reinterpret_cast<const BatchItem*>(base + off_t1);
-  a.n_trmv[0] = (int)trmv[0].size();
-  a.n_trmv[1] = (int)trmv[1].size();
+  a.symv_items = reinterpret_cast<const BatchItem*>(base + off_symv);
+  a.xupd_items = reinterpret_cast<const BatchItem*>(base + off_xupd);
+  a.n_symv = (int)symv.size();
+  a.n_xupd = (int)xupd.size();
   a.stream_items = reinterpret_cast<const BatchItem*>(base + off_stream);
   a.n_stream = (int)stream.size();
   a.prime_items = reinterpret_cast<const BatchItem*>(base + off_prime);

@@ -171,20 +171,47 @@ struct GramArgs {
 };
 hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s);
 
+// Tiled inverse P_ij = K_ij^-1 (FP64), the operator of the x_ij-step.  Block
+// (i, j) holds the 64 x 64 tiles (I, J), I >= J, of the lower block triangle of
+// P_ij (T = ceil(n_j / 64) tiles per side), tile t = I (I + 1) / 2 + J at
+// kinv + fac_off[i M + j] + t * 4096; diagonal tiles are stored in full and
+// entries outside n_j x n_j are zero.  Inside a tile, element (row, col) sits at
+// ptile_pos(row, col): lane l of a wavefront reads rows 16 q + 2 (l / 8) + {0, 1}
+// and columns 8 (l % 8) .. 8 (l % 8) + 7 of row chunk q with 8 coalesced 16-byte
+// loads (vector k = 4 (row % 2) + (col % 8) / 2 of the chunk).
+constexpr int PT = 64;
+constexpr int PT_ELEMS = PT * PT;
+__host__ __device__ __forceinline__ int ptile_pos(int row, int col) {
+  const int q = row >> 4, l = 8 * ((row & 15) >> 1) + (col >> 3);
+  const int k = 4 * (row & 1) + ((col & 7) >> 1);
+  return ((q * 8 + k) * 64 + l) * 2 + (col & 1);
+}
+__host__ __device__ __forceinline__ int64_t ptile_count(int nj) {
+  const int64_t T = (nj + PT - 1) / PT;
+  return T * (T + 1) / 2;
+}
+// Lower-triangular tile index t -> (ti, tj), ti >= tj.
+__device__ __forceinline__ void tri_tile(int t, int* ti, int* tj) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *ti = i;
+  *tj = t - i * (i + 1) / 2;
+}
+
 struct FactorArgs {
   double* kbuf;            // in: K_ij (lower); out: L_ij (lower)
-  double* wbuf;            // out: W_ij = L_ij^-1 dense (lower)
+  double* wbuf;            // out: W_ij = L_ij^-1 dense (lower, upper part zero)
   const int64_t* kmat_off; // N*M
   const int32_t* col_off;  // M + 1
-  double* wr;              // packed lower rows of W_ij
-  double* wc;              // packed lower columns of W_ij (rows of W_ij^T)
-  const int64_t* fac_off;  // N*M offsets (doubles) into wr / wc
+  double* kinv;            // out: tiled P_ij = W_ij^T W_ij
+  const int64_t* fac_off;  // N*M offsets (doubles) into kinv
   int* status;             // set nonzero if a pivot is not positive
   int N, M, nj_max;
 };
 hipError_t launch_cholesky(const FactorArgs& a, hipStream_t s);
 hipError_t launch_inverse(const FactorArgs& a, hipStream_t s);
-hipError_t launch_pack(const FactorArgs& a, hipStream_t s);
+hipError_t launch_kinv(const FactorArgs& a, hipStream_t s);
 
 struct SolveArgs {
   const double* gpart;     // N x Gp x ld x C
@@ -197,9 +224,8 @@ struct SolveArgs {
   const double* u;         // N x n x C
   const double* z;         // n x C
   double* rhs;             // N x n x C
-  double* tmp;             // N x n x C
-  const double* wr;
-  const double* wc;
+  double* ypart;           // N*M blocks x (tmax x tmax slots x 64 x C) partial products
+  const double* kinv;      // tiled P_ij
   const int64_t* fac_off;  // N*M
   const int32_t* col_off;  // M + 1
   int N, M, n, C, nj_max;
@@ -250,12 +276,11 @@ struct BatchInst {
   int* status;
   double* gpart;           // N x (items_per_part * 4) x ld wave partials of A^T e
   double* rhs;             // N x n right-hand sides of the x_ij-step
-  double* y;               // N x n intermediate W r of the x_ij-step
-  const double* wr;
-  const double* wc;
+  double* ypart;           // N*M blocks x (tmax x tmax slots x 64) partial products
+  const double* kinv;      // tiled P_ij = K_ij^-1
   const int64_t* fac_off;
   const int32_t* col_off;
-  int N, M, n, kappa, loss, dtype, nvec, hist_cap, inner_iters;
+  int N, M, n, kappa, loss, dtype, nvec, hist_cap, inner_iters, tmax;
   int rows_per_item, items_per_part, shape;   // stream tile shape (see batch.hip)
   int outer;               // outer iterations this launch runs for the problem
   double rho_l, rho_c, rho_b, shift, inv_M;
@@ -270,8 +295,10 @@ struct BatchArgs {
   int count;
   const BatchItem* rhs_items;      // (inst, partition, block), largest first
   int n_rhs;
-  const BatchItem* trmv_items[2];  // (inst, partition, block, first row, end row): y = W r, x += W^T y
-  int n_trmv[2];
+  const BatchItem* symv_items;     // (inst, partition, block, first tile, end tile)
+  int n_symv;
+  const BatchItem* xupd_items;     // (inst, partition, block)
+  int n_xupd;
   const BatchItem* stream_items;   // (inst, partition, chunk), largest first
   int n_stream;
   const BatchItem* prime_items;    // stream items of problems whose partial sums are stale

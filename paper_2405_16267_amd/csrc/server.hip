@@ -68,8 +68,10 @@ size_t footprint(const bca_params& p, const std::vector<int64_t>& rows) {
   const int64_t nj = (n + M - 1) / M;
   size_t b = (size_t)m * ld * esize(p.a_dtype);       // A
   b += (size_t)m * 8 * (1 + 2 * C + (C > 1 ? C : 0));  // b, omega, nu (and the multi-class row buffer)
-  b += (size_t)N * n * C * 8 * 4 + (size_t)N * ld * C * 8;   // x, u, rhs, tmp, xs
-  b += (size_t)N * M * nj * (nj + 1) * 8;             // packed inverse factors (two copies)
+  const int64_t T = (nj + 63) / 64;
+  b += (size_t)N * n * C * 8 * 3 + (size_t)N * ld * C * 8;   // x, u, rhs, xs
+  b += (size_t)N * M * T * (T + 1) / 2 * 4096 * 8;   // tiled inverses K_ij^-1
+  b += (size_t)N * M * T * T * 64 * C * 8;            // slots of the symmetric products
   b += (size_t)N * M * nj * nj * 8 * 2;               // finalize work space (released after)
   int64_t mx = 0;
   for (auto r : rows) mx = std::max(mx, r);

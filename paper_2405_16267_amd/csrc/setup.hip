@@ -1,19 +1,22 @@
 // One-time setup of the x_ij-step of Sec. 3.1: the ridge problem of every
 // feature block is K_ij x = rhs with
-//     K_ij = rho_l A_ij^T A_ij + (1/(N gamma) + rho_c) I,
-// whose Cholesky factor L_ij is cached.  The triangular solves with L_ij are
-// applied as products with the cached inverse factor W_ij = L_ij^-1 (computed
-// here once in FP64), which turns a sequential substitution into a fully
-// parallel triangular matrix-vector product with the same bytes moved.
+//     K_ij = rho_l A_ij^T A_ij + (1/(N gamma) + rho_c) I.
+// Its Cholesky factor L_ij, the inverse factor W_ij = L_ij^-1 and from it the
+// inverse P_ij = K_ij^-1 = W_ij^T W_ij are computed here once in FP64; the
+// iterations then apply P_ij as one symmetric matrix-vector product per block,
+// which reads each stored entry once (the two triangular solves with L_ij would
+// be sequential, and two triangular products with W_ij read twice the bytes).
 //
-//   gram_kernel      G_ij = A_ij^T A_ij on MFMA (FP64, FP32 or BF16 inputs,
-//                    FP64/FP32 accumulation), lower 64x64 tiles, epilogue
-//                    writes K_ij in FP64.
-//   cholesky_kernel  right-looking blocked Cholesky (32-wide panels) of K_ij in
-//                    FP64, one workgroup per block.
-//   inverse_kernel   W_ij = L_ij^-1 by blocked forward substitution on the
-//                    identity, one workgroup per 64-column block of W.
-//   pack_kernel      packed lower rows (W) and packed lower columns (W^T rows).
+//   gram_kernel / gram128_kernel
+//                    G_ij = A_ij^T A_ij on MFMA (FP64, FP32 or BF16 inputs,
+//                    FP64/FP32 accumulation), lower tiles, epilogue writes K_ij
+//                    in FP64.
+//   chol_*_kernel    right-looking blocked Cholesky (32-wide panels) of all
+//                    blocks at once, FP64.
+//   inv_*_kernel     W_ij = L_ij^-1 right-looking by 64-row blocks, FP64.
+//   kinv_kernel      P_ij = W_ij^T W_ij on FP64 MFMA, written as the tiled
+//                    symmetric layout the solve reads (64 x 64 tiles of the
+//                    lower block triangle, diagonal tiles in full).
 #include "bca_internal.h"
 
 namespace bca {
@@ -81,15 +84,6 @@ struct GramMfma<bf16_t> {
   __device__ static double out(const acc_t& c, int v) { return (double)c[v]; }
   __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
-
-// Lower-triangular tile index t -> (ti, tj), ti >= tj.
-__device__ __forceinline__ void tri_tile(int t, int* ti, int* tj) {
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  *ti = i;
-  *tj = t - i * (i + 1) / 2;
-}
 
 // 64x64 output tile per workgroup of 256 threads; wave w computes the 32x32
 // quadrant (w / 2, w % 2) as 2 x 2 MFMA tiles.  LDS holds the two 64-column
@@ -677,28 +671,85 @@ hipError_t launch_inverse(const FactorArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ packing
-// wr: row r of W (columns 0..r) at r (r + 1) / 2.
-// wc: column c of W (rows c..n-1) at c n - c (c - 1) / 2.
-__global__ __launch_bounds__(256) void pack_kernel(FactorArgs a) {
+// ------------------------------------------------------------------ P = W^T W
+// Tile (I, J), I >= J, of P_ij: P[i][j] = sum_k W[k][i] W[k][j].  W is lower
+// triangular, so rows k < 64 I (< every i of the tile) contribute nothing and the
+// contraction runs over rows 64 I .. n_j - 1 only.  Same MFMA scheme as
+// gram_kernel<double> (64 x 64 tile per workgroup, a 32 x 32 quadrant per
+// wavefront, the two 64-column panels of a 16-row chunk staged transposed in LDS);
+// the epilogue writes the whole tile, zeros outside n_j x n_j.
+__global__ __launch_bounds__(256) void kinv_kernel(FactorArgs a) {
+  using MF = GramMfma<double>;
+  constexpr int KB = MF::KB;
+  constexpr int LS = KB + MF::PAD;
+  __shared__ double sI[64 * LS];
+  __shared__ double sJ[64 * LS];
   const int bid = blockIdx.y;
   const int blk = bid % a.M;
   const int n = a.col_off[blk + 1] - a.col_off[blk];
+  const int T_ = (n + PT - 1) / PT;
+  int ti, tj;
+  tri_tile(blockIdx.x, &ti, &tj);
+  if (ti >= T_) return;
   const double* W = a.wbuf + a.kmat_off[bid];
-  double* wr = a.wr + a.fac_off[bid];
-  double* wc = a.wc + a.fac_off[bid];
-  for (int r = blockIdx.x; r < n; r += gridDim.x) {
-    for (int c = threadIdx.x; c <= r; c += 256) {
-      const double v = W[(int64_t)r * n + c];
-      wr[(int64_t)r * (r + 1) / 2 + c] = v;
-      wc[(int64_t)c * n - (int64_t)c * (c - 1) / 2 + (r - c)] = v;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = wv >> 1, wc = wv & 1;
+  const bool diag = (ti == tj);
+  MF::acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = 0.0;
+  for (int k0 = ti * PT; k0 < n; k0 += KB) {
+    for (int idx = tid; idx < KB * 64; idx += 256) {
+      const int k = idx >> 6, c = idx & 63;
+      const int row = k0 + k;
+      const int ci = ti * PT + c, cj = tj * PT + c;
+      double vi = 0.0, vj = 0.0;
+      if (row < n) {
+        if (ci < n) vi = W[(int64_t)row * n + ci];
+        if (!diag && cj < n) vj = W[(int64_t)row * n + cj];
+      }
+      sI[c * LS + k] = vi;
+      if (!diag) sJ[c * LS + k] = vj;
     }
+    __syncthreads();
+    const double* pJ = diag ? sI : sJ;
+#pragma unroll
+    for (int ks = 0; ks < KB; ks += MF::K_STEP) {
+      const int kk = ks + MF::K_PER_LANE * (lane >> 4);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const double* pa = sI + (wr * 32 + x * 16 + (lane & 15)) * LS + kk;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const double* pb = pJ + (wc * 32 + y * 16 + (lane & 15)) * LS + kk;
+          MF::mma(acc[x][y], pa, pb);
+        }
+      }
+    }
+    __syncthreads();
   }
+  double* out = a.kinv + a.fac_off[bid] + (int64_t)blockIdx.x * PT_ELEMS;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 32 + x * 16 + MF::out_row(lane, v);
+        const int col = wc * 32 + y * 16 + (lane & 15);
+        const bool in = ti * PT + row < n && tj * PT + col < n;
+        out[ptile_pos(row, col)] = in ? MF::out(acc[x][y], v) : 0.0;
+      }
 }
 
-hipError_t launch_pack(const FactorArgs& a, hipStream_t s) {
-  dim3 grid(256, a.N * a.M);
-  hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, s, a);
+hipError_t launch_kinv(const FactorArgs& a, hipStream_t s) {
+  const int T_ = (a.nj_max + PT - 1) / PT;
+  dim3 grid(T_ * (T_ + 1) / 2, a.N * a.M);
+  hipLaunchKernelGGL(kinv_kernel, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,111 @@
+// Symmetric product y = P r of the x_ij-step, one 64 x 64 tile per wavefront
+// (shared by the one-problem solve and the batched kernel).
+//
+// P is stored as the tiles (I, J), I >= J, of its lower block triangle (layout in
+// bca_internal.h).  An off-diagonal tile contributes P_IJ r_J to rows I and
+// P_IJ^T r_I to rows J, so every stored entry is read once and used twice; a
+// diagonal tile (stored in full) contributes P_II r_I.  Each contribution is a
+// 64-vector written to its own slot, slot (R, S) = the part of y_R that comes
+// from the tile pair of block rows R and S, so the final sum over S runs in a
+// fixed order and the result is bitwise reproducible.
+#pragma once
+
+#include "bca_internal.h"
+
+namespace bca {
+
+typedef double symv_d2 __attribute__((ext_vector_type(2)));
+
+// tile: this tile's 4096 doubles; r: the block's right-hand sides (n_j x C,
+// feature-major); ys: the block's slots, slot (R, S) at ys + (R T + S) 64 C.
+// Lane l = 8 a + b holds rows 16 q + 2 a + h (q < 4, h < 2) and columns
+// 8 b .. 8 b + 7 of the tile.  Row sums are reduced over the 8 lanes of equal a
+// (DPP), column sums over the 8 lanes of equal b.
+__device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const double* __restrict__ r,
+                                          int nj, int C, int I, int J, int T, double* __restrict__ ys) {
+  const int lane = threadIdx.x & 63;
+  const int a = lane >> 3, b = lane & 7;
+  const bool diag = I == J;
+  symv_d2 p[4][8];
+  const symv_d2* tp = reinterpret_cast<const symv_d2*>(tile) + lane;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[q][k] = tp[(q * 8 + k) * 64];
+  const int colJ = PT * J + 8 * b, rowI = PT * I + 2 * a;
+  for (int c = 0; c < C; ++c) {
+    // indices past n_j are clamped: the tile is zero there
+    double rj[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rj[e] = r[(int64_t)min(colJ + e, nj - 1) * C + c];
+    double rs[8], cs[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cs[e] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          s += p[q][4 * h + v][0] * rj[2 * v];
+          s += p[q][4 * h + v][1] * rj[2 * v + 1];
+        }
+        rs[2 * q + h] = s;
+      }
+      if (!diag) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double ri = r[(int64_t)min(rowI + 16 * q + h, nj - 1) * C + c];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cs[2 * v] += p[q][4 * h + v][0] * ri;
+            cs[2 * v + 1] += p[q][4 * h + v][1] * ri;
+          }
+        }
+      }
+    }
+    // row sums: xor 1, xor 2, then the mirrored half of the 8-lane group
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      rs[e] += dpp_f64<0xB1>(rs[e]);
+      rs[e] += dpp_f64<0x4E>(rs[e]);
+      rs[e] += dpp_f64<0x141>(rs[e]);
+    }
+    // lane (a, b) writes row 16 (b / 2) + 2 a + b % 2, i.e. rs[b]
+    double rv = rs[0];
+#pragma unroll
+    for (int e = 1; e < 8; ++e) rv = b == e ? rs[e] : rv;
+    const int row = 16 * (b >> 1) + 2 * a + (b & 1);
+    ys[(((int64_t)I * T + J) * PT + row) * C + c] = rv;
+    if (!diag) {
+      // column sums over a: xor 8 (rotate by 8 inside each row of 16 lanes), 16, 32
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        cs[e] += dpp_f64<0x128>(cs[e]);
+        cs[e] += __shfl_xor(cs[e], 16, 64);
+        cs[e] += __shfl_xor(cs[e], 32, 64);
+      }
+      // lane (a, b) writes column 8 b + a, i.e. cs[a]
+      double cv = cs[0];
+#pragma unroll
+      for (int e = 1; e < 8; ++e) cv = a == e ? cs[e] : cv;
+      ys[(((int64_t)J * T + I) * PT + 8 * b + a) * C + c] = cv;
+    }
+  }
+}
+
+// y_i = sum over S of slot (i / 64, S) entry i % 64, S = 0 .. T - 1 in order.
+__device__ __forceinline__ double symv_gather(const double* __restrict__ ys, int i, int c, int C, int T) {
+  const double* p = ys + ((int64_t)(i >> 6) * T * PT + (i & 63)) * C + c;
+  double y0 = 0.0, y1 = 0.0;
+  int S = 0;
+  for (; S + 2 <= T; S += 2) {
+    y0 += p[(int64_t)S * PT * C];
+    y1 += p[(int64_t)(S + 1) * PT * C];
+  }
+  if (S < T) y0 += p[(int64_t)S * PT * C];
+  return y0 + y1;
+}
+
+}  // namespace bca

@@ -54,11 +54,11 @@ def rel(a, b):
 
 # ------------------------------------------------------------------ setup: Gram, Cholesky, inverse
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-def test_inverse_factor_matches_ridge_matrix(dtype):
-    """W_ij^T W_ij K_ij = I, with K_ij = rho_l A_ij^T A_ij + (1/(N gamma) + rho_c) I
+def test_cached_inverse_matches_ridge_matrix(dtype):
+    """P_ij K_ij = I, with K_ij = rho_l A_ij^T A_ij + (1/(N gamma) + rho_c) I
     formed on the host from the stored data: pins the MFMA Gram, the Cholesky
-    factor and the triangular inverse together.  n_j = 150 and 149 span three
-    64-wide tiles with a ragged tail."""
+    factor, the triangular inverse, P = W^T W and its tiled storage together.
+    n_j = 150 and 149 span three 64-wide tiles with a ragged tail."""
     w = datagen.linear_workload(21, N=2, m_per=[333, 290], n=299, kappa=5, k_true=5, noise=0.1,
                                 n_blocks=2, dtype=dtype, max_iters=3, rho=1.3)
     P = make_gpu(w)
@@ -69,9 +69,9 @@ def test_inverse_factor_matches_ridge_matrix(dtype):
         for j, (c0, c1) in enumerate(bounds):
             Aj = A[:, c0:c1]
             K = w.rho_l * Aj.T @ Aj + (1.0 / (w.N * w.gamma) + w.rho_c) * np.eye(c1 - c0)
-            W = P.factor(i, j)
-            assert np.allclose(np.triu(W, 1), 0.0)
-            E = W.T @ W @ K - np.eye(c1 - c0)
+            Kinv = P.inverse(i, j)
+            assert np.max(np.abs(Kinv - Kinv.T)) < 1e-14 * np.max(np.abs(Kinv))
+            E = Kinv @ K - np.eye(c1 - c0)
             assert np.max(np.abs(E)) < tol, (i, j, np.max(np.abs(E)))
     P.close()
 

@@ -112,7 +112,10 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
           else
             d += vget(v[r][q], e) * xr[q][e];
         }
-      dd[r] = wave_sum((double)d);
+      // BF16 (heavier per-chunk arithmetic): DPP lane moves and four read-outs
+      // instead of six LDS permutes, +4 % on the streaming pass; for FP32 rows
+      // the permutes measured slightly faster
+      dd[r] = VEC == 8 ? wave_sum_dpp((double)d) : wave_sum((double)d);
     }
     if (lane == 0) {
 #pragma unroll

@@ -211,14 +211,16 @@ int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream);
 
 /* Tile-shape autotuner of the batched streaming pass: groups the problems by
  * (storage type, row length, rows per partition), times every candidate shape
- * (rows per wavefront tile 1/2/4 x rows per work item 64/256/1024; a work item is
- * one wavefront's chunk of rows) on each group
+ * (rows per wavefront tile 1/2/4, and 8 for rows of at most 64 16-byte chunks,
+ * x rows per work item 64/256/1024; a work item is one wavefront's chunk of rows)
+ * on each group
  * with a state-preserving streaming pass, and keeps the fastest per group.  The
  * ADMM state is not modified. */
 int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream);
 
 /* Explicit tile shape of a problem in the batched form (rows per wavefront tile
- * 1, 2 or 4; rows per work item >= 16) and its current value. */
+ * 1, 2, 4 or 8 -- 8 only for rows of at most 64 16-byte chunks; rows per work
+ * item >= 16) and its current value.  BCA_E_INVALID if no such shape is built. */
 int bca_batch_set_shape(bca_problem p, int32_t rows_per_tile, int32_t rows_per_item);
 int bca_batch_get_shape(bca_problem p, int32_t* rows_per_tile, int32_t* rows_per_item);
 

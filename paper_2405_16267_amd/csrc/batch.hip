@@ -27,8 +27,9 @@
 // Stream tile shapes: chunks per lane NC (a row of nvec 16-byte chunks is read by
 // one wavefront, NC = ceil(nvec / 64) rounded up to 1, 2, 4 or 8, or by a
 // segment of 16 or 32 lanes for rows of at most 16 or 32 chunks) and rows per
-// segment tile R in {1, 2, 4} with R NC <= 8, which bounds the kernel's register
-// footprint; rows per item is a runtime parameter.
+// segment tile R in {1, 2, 4} with R NC <= 8 (and R = 8 for one-chunk rows, whose
+// tiles are otherwise too small to keep enough bytes in flight), which bounds the
+// kernel's register footprint; rows per item is a runtime parameter.
 // The shape of each problem is picked by the autotuner in bca_api.hip.
 #include <hip/hip_cooperative_groups.h>
 
@@ -48,10 +49,10 @@ constexpr int BW = BT / 64;
 // wavefront is split into S segments of 64 / S lanes, each streaming its own rows,
 // so that rows of at most 16 or 32 chunks (short feature vectors) still keep
 // every lane busy; S follows from the row length, R is tuned.
-constexpr int kShapes = 15;
-static const int kShapeNC[kShapes] = {1, 1, 1, 2, 2, 2, 4, 4, 8, 1, 1, 1, 1, 1, 1};
-static const int kShapeR[kShapes] = {1, 2, 4, 1, 2, 4, 1, 2, 1, 1, 2, 4, 1, 2, 4};
-static const int kShapeS[kShapes] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 4, 4, 4};
+constexpr int kShapes = 18;
+static const int kShapeNC[kShapes] = {1, 1, 1, 2, 2, 2, 4, 4, 8, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+static const int kShapeR[kShapes] = {1, 2, 4, 1, 2, 4, 1, 2, 1, 1, 2, 4, 1, 2, 4, 8, 8, 8};
+static const int kShapeS[kShapes] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 4, 4, 4, 1, 2, 4};
 
 int batch_max_nvec() { return 64 * 8; }
 
@@ -254,7 +255,10 @@ __device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, in
     case 11: stream_item<T, 1, 4, 2>(I, part, chunk, mode, lg); break;
     case 12: stream_item<T, 1, 1, 4>(I, part, chunk, mode, lg); break;
     case 13: stream_item<T, 1, 2, 4>(I, part, chunk, mode, lg); break;
-    default: stream_item<T, 1, 4, 4>(I, part, chunk, mode, lg); break;
+    case 14: stream_item<T, 1, 4, 4>(I, part, chunk, mode, lg); break;
+    case 15: stream_item<T, 1, 8, 1>(I, part, chunk, mode, lg); break;
+    case 16: stream_item<T, 1, 8, 2>(I, part, chunk, mode, lg); break;
+    default: stream_item<T, 1, 8, 4>(I, part, chunk, mode, lg); break;
   }
 }
 

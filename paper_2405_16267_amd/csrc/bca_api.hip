@@ -1198,8 +1198,8 @@ int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream) {
 
 int bca_batch_set_shape(bca_problem P, int32_t rows_per_tile, int32_t rows_per_item) {
   if (!P) return fail(BCA_E_INVALID, "null problem");
-  if (rows_per_tile != 1 && rows_per_tile != 2 && rows_per_tile != 4)
-    return fail(BCA_E_INVALID, "rows_per_tile must be 1, 2 or 4");
+  if (rows_per_tile != 1 && rows_per_tile != 2 && rows_per_tile != 4 && rows_per_tile != 8)
+    return fail(BCA_E_INVALID, "rows_per_tile must be 1, 2, 4 or 8");
   if (rows_per_item < 16 || rows_per_item > (1 << 20)) return fail(BCA_E_INVALID, "rows_per_item out of range");
   if (batch_shape_code(P->nvec, rows_per_tile) < 0)
     return fail(BCA_E_INVALID, "no batched tile shape with %d rows per tile for n = %d", rows_per_tile, P->n);
@@ -1242,14 +1242,14 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
     }
     buckets[b].push_back(P);
   }
-  const int tiles[3] = {1, 2, 4};
+  const int tiles[4] = {1, 2, 4, 8};
   const int items[3] = {64, 256, 1024};
   for (size_t b = 0; b < buckets.size(); ++b) {
     auto& bp = buckets[b];
     for (auto P : bp) TRY(batch_check_basic(P));
     float best = 1e30f;
     int bt = 2, bi = 256;
-    for (int ti = 0; ti < 3; ++ti) {
+    for (int ti = 0; ti < 4; ++ti) {
       if (batch_shape_code(bp[0]->nvec, tiles[ti]) < 0) continue;
       for (int ii = 0; ii < 3; ++ii) {
         for (auto P : bp) {

@@ -127,7 +127,7 @@ def test_batch_autotune_keeps_state_and_results():
     for p, zb in zip(P, z_before):
         assert np.array_equal(p.get_vector(bca.VEC_Z), zb)
         t, i = p.batch_shape()
-        assert t in (1, 2, 4) and i in (64, 256, 1024)
+        assert t in (1, 2, 4, 8) and i in (64, 256, 1024)
     bca.batch_step(P, 3)
     bca.batch_step(Q, 3)
     for p, q in zip(P, Q):

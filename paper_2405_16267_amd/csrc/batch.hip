@@ -5,24 +5,26 @@
 // one-problem path (Algorithm 2's K_in inner iterations, then the global step
 // of Algorithm 1), but here each phase is a list of independent work items
 // spanning all problems:
-//   RHS     item (problem, partition, block): the FP64 reduction of that block's
-//           A^T e partial sums into the right-hand side of the x_ij-step;
+//   RHS     item (problem, partition, block, 64 columns): the FP64 reduction of
+//           the A^T e partial sums into the right-hand side of the x_ij-step;
 //   SYMV    item (problem, partition, block, tile range): one wavefront applies
 //           tiles of the cached inverse P_ij = K_ij^-1 to r (symmetric product,
 //           each stored tile read once), so a large block is shared by many
 //           wavefronts;
-//   XUPD    item (problem, partition, block): x += P_ij r from the product's
-//           slots, in a fixed order, and the streaming copy of x;
+//   XUPD    item (problem, partition, block, 64 rows): x += P_ij r from the
+//           product's slots, in a fixed order, and the streaming copy of x;
 //   STREAM  item (problem, partition, row chunk): the fused streaming pass over
 //           a chunk of rows by one wavefront (block predictions, sample-space
 //           average, omega-bar prox, nu update, e, partial A^T e of the chunk);
 //   GLOBAL  item (problem): consensus average, exact (z,t) step, top-kappa
 //           s-step, v and u updates, residuals.
-// The workgroups (wavefronts, for stream items) of the persistent grid claim
-// items of the current phase with an atomic counter (largest items first) and
-// meet at a grid barrier between phases.  A problem's results depend only on its own items (fixed reduction
-// orders inside each item, tile shape chosen per problem shape, never per
-// batch), so a problem computes the same bits alone and inside any batch.
+// The wavefronts of the persistent grid take the items of the current phase
+// (largest first: stream items through an atomic counter, solve items
+// round-robin; global items per workgroup through a counter) and meet at a grid
+// barrier between phases.  A problem's results depend only on its own items
+// (fixed reduction orders inside each item, tile shape chosen per problem shape,
+// never per batch), so a problem computes the same bits alone and inside any
+// batch.
 //
 // Stream tile shapes: chunks per lane NC (a row of nvec 16-byte chunks is read by
 // one wavefront, NC = ceil(nvec / 64) rounded up to 1, 2, 4 or 8, or by a
@@ -262,30 +264,33 @@ __device__ void stream_item_dispatch(const BatchInst& I, int part, int chunk, in
   }
 }
 
-// x_ij-step of one block, in three phases of independent items so that a large
-// block's inverse is read by many wavefronts at once:
-//   RHS  (partition, block): r = rho_l sum_w gpart_w + rho_c (z - u) - shift x;
+// x_ij-step of one block, in three phases of independent items, each claimed by
+// one wavefront, so that a large block is spread over many wavefronts:
+//   RHS  (partition, block, 64 columns): r = rho_l sum_w gpart_w + rho_c (z - u) - shift x;
 //   SYMV (partition, block, tile range): slots of y = P_ij r (symv_impl.h);
-//   XUPD (partition, block): x += y, y summed from the slots in a fixed order.
-__device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk) {
+//   XUPD (partition, block, 64-row slot row): x += y, y summed from the slots in a
+//        fixed order.
+__device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk, int cbeg) {
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
+  const int c = cbeg + (threadIdx.x & 63);
+  if (c >= nj) return;
   const int P = I.items_per_part;
-  const double* gb = I.gpart + (int64_t)part * P * I.ld;
-  for (int c = threadIdx.x; c < nj; c += BT) {
-    const int k = c0 + c;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int w = 0;
-    for (; w + 4 <= P; w += 4) {
-      s0 += gb[(int64_t)w * I.ld + k];
-      s1 += gb[(int64_t)(w + 1) * I.ld + k];
-      s2 += gb[(int64_t)(w + 2) * I.ld + k];
-      s3 += gb[(int64_t)(w + 3) * I.ld + k];
-    }
-    for (; w < P; ++w) s0 += gb[(int64_t)w * I.ld + k];
-    const int64_t o = (int64_t)part * I.n + k;
-    I.rhs[o] = I.rho_l * ((s0 + s1) + (s2 + s3)) + I.rho_c * (I.z[k] - I.u[o]) - I.shift * I.x[o];
+  const int k = c0 + c;
+  const double* gb = I.gpart + (int64_t)part * P * I.ld + k;
+  // eight partial sums, so eight loads per lane are in flight
+  double s[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  int w = 0;
+  for (; w + 8 <= P; w += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += gb[(int64_t)(w + u) * I.ld];
   }
+  for (; w < P; ++w) s[0] += gb[(int64_t)w * I.ld];
+  const double ate = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  const int64_t o = (int64_t)part * I.n + k;
+  I.rhs[o] = I.rho_l * ate + I.rho_c * (I.z[k] - I.u[o]) - I.shift * I.x[o];
 }
 
 // Tiles [t0, t1) of block (part, blk), one after the other, by one wavefront.
@@ -304,24 +309,23 @@ __device__ __noinline__ void symv_item(const BatchInst& I, int part, int blk, in
   }
 }
 
-// x += y over the block's n_j features by one wavefront.
-__device__ __noinline__ void xupd_item(const BatchInst& I, int part, int blk) {
+// x += y over the 64 features of slot row R of block (part, blk).
+__device__ __noinline__ void xupd_item(const BatchInst& I, int part, int blk, int R) {
   const int bid = part * I.M + blk;
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
+  const int i = R * PT + (threadIdx.x & 63);
+  if (i >= nj) return;
   const int T = (nj + PT - 1) / PT;
-  const double* ys = I.ypart + (int64_t)bid * I.tmax * I.tmax * PT;
-  for (int i = threadIdx.x & 63; i < nj; i += 64) {
-    const double y = symv_gather(ys, i, 0, 1, T);
-    const int64_t o = (int64_t)part * I.n + c0 + i;
-    const double xn = I.x[o] + y;
-    I.x[o] = xn;
-    const int64_t so = (int64_t)part * I.ld + c0 + i;
-    if (I.dtype == BCA_F64)
-      reinterpret_cast<double*>(I.xs)[so] = xn;
-    else
-      reinterpret_cast<float*>(I.xs)[so] = (float)xn;
-  }
+  const double y = symv_gather(I.ypart + (int64_t)bid * I.tmax * I.tmax * PT, i, 0, 1, T);
+  const int64_t o = (int64_t)part * I.n + c0 + i;
+  const double xn = I.x[o] + y;
+  I.x[o] = xn;
+  const int64_t so = (int64_t)part * I.ld + c0 + i;
+  if (I.dtype == BCA_F64)
+    reinterpret_cast<double*>(I.xs)[so] = xn;
+  else
+    reinterpret_cast<float*>(I.xs)[so] = (float)xn;
 }
 
 // Out of line, with 7 multisection points per round, so that the global step's
@@ -370,14 +374,18 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
     __syncthreads();
     return it;
   };
-  // stream and symmetric-product items are claimed by single wavefronts (no
+  // The items of the solve and stream phases go to single wavefronts (no
   // workgroup barrier between items, so the 8 wavefronts of a CU overlap their
-  // per-item latencies)
+  // per-item latencies).  Stream items, whose costs vary with the tile shape,
+  // are claimed with an atomic counter; the many small solve items are dealt
+  // round-robin over the wavefronts of the grid (largest first), since a claim
+  // costs about as much as such an item and the claims of one counter serialise.
   auto claim_wave = [&]() {
     int it = 0;
     if ((threadIdx.x & 63) == 0) it = (int)atomicAdd(&ba.counters[phase], 1u);
     return __shfl(it, 0, 64);
   };
+  const int gwave = blockIdx.x * BW + (threadIdx.x >> 6), nwaves = gridDim.x * BW;
   auto run_stream = [&](const BatchItem* items, int count, int mode, int k_inner, int o) {
     for (int it = claim_wave(); it < count; it = claim_wave()) {
       const BatchItem w = items[it];
@@ -398,15 +406,15 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
   }
   for (int o = 0; o < ba.outer; ++o) {
     for (int k = 0; k < ba.inner_max; ++k) {
-      for (int it = claim(); it < ba.n_rhs; it = claim()) {
+      for (int it = gwave; it < ba.n_rhs; it += nwaves) {
         const BatchItem w = ba.rhs_items[it];
         const BatchInst& I = ba.inst[w.inst];
         if (o >= I.outer || k >= I.inner_iters) continue;
-        rhs_item(I, w.a, w.b);
+        rhs_item(I, w.a, w.b, w.c);
       }
       ++phase;
       grid.sync();
-      for (int it = claim_wave(); it < ba.n_symv; it = claim_wave()) {
+      for (int it = gwave; it < ba.n_symv; it += nwaves) {
         const BatchItem w = ba.symv_items[it];
         const BatchInst& I = ba.inst[w.inst];
         if (o >= I.outer || k >= I.inner_iters) continue;
@@ -414,11 +422,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
       }
       ++phase;
       grid.sync();
-      for (int it = claim_wave(); it < ba.n_xupd; it = claim_wave()) {
+      for (int it = gwave; it < ba.n_xupd; it += nwaves) {
         const BatchItem w = ba.xupd_items[it];
         const BatchInst& I = ba.inst[w.inst];
         if (o >= I.outer || k >= I.inner_iters) continue;
-        xupd_item(I, w.a, w.b);
+        xupd_item(I, w.a, w.b, w.c);
       }
       ++phase;
       grid.sync();

@@ -1044,9 +1044,10 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     const int ipp = desc[r].items_per_part;
     for (int i = 0; i < P->N; ++i) {
       for (int j = 0; j < P->M; ++j) {
-        solve.push_back({r, i, j, 0, 0});
-        xupd.push_back({r, i, j, 0, 0});
-        const int nt = (int)ptile_count(P->col_off[j + 1] - P->col_off[j]);
+        const int nj = P->col_off[j + 1] - P->col_off[j];
+        for (int c = 0; c < nj; c += PT) solve.push_back({r, i, j, c, 0});
+        for (int R = 0; R * PT < nj; ++R) xupd.push_back({r, i, j, R, 0});
+        const int nt = (int)ptile_count(nj);
         for (int t0 = 0; t0 < nt; t0 += kSymvTiles) symv.push_back({r, i, j, t0, std::min(nt, t0 + kSymvTiles)});
       }
       for (int c = 0; c < ipp; ++c) {
@@ -1055,17 +1056,12 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
       }
     }
   }
-  // largest work first: rhs and update items by n_j (x partials), product items
-  // by tiles, stream items by rows x vectors
-  auto solve_cost = [&](const BatchItem& w) {
-    bca_problem P = probs[w.inst];
-    const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
-    return nj * batch_items_per_part(P);
-  };
+  // largest work first: rhs items by partial sums per column, update items by
+  // slots per row, product items by tiles, stream items by rows x vectors
+  auto solve_cost = [&](const BatchItem& w) { return batch_items_per_part(probs[w.inst]); };
   auto xupd_cost = [&](const BatchItem& w) {
     bca_problem P = probs[w.inst];
-    const int64_t nj = P->col_off[w.b + 1] - P->col_off[w.b];
-    return nj * ((nj + PT - 1) / PT);
+    return (int64_t)(P->col_off[w.b + 1] - P->col_off[w.b] + PT - 1) / PT;
   };
   std::stable_sort(symv.begin(), symv.end(), [](const BatchItem& a, const BatchItem& b) {
     return a.d - a.c > b.d - b.c;

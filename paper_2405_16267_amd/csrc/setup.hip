@@ -26,6 +26,17 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ Gram
+// Linear work-group id remapped so that each of the 8 XCDs (work-groups are
+// dispatched to them round-robin by linear id) takes one contiguous range of the
+// grid's work: neighbouring tiles, which share operand panels, then run on the
+// same XCD and meet in its L2.  A bijection on [0, total).
+__device__ __forceinline__ int xcd_remap(int id, int total) {
+  constexpr int X = 8;
+  const int xcd = id % X, slot = id / X;
+  const int q = total / X, r = total % X;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
 // MFMA shapes: 16x16 output per instruction, K_STEP contraction rows per
 // instruction.  Operand layout (lane l): A-side element (i = l % 16,
 // k = K_PER_LANE * (l / 16) + e), B-side element (k likewise, j = l % 16).
@@ -244,13 +255,16 @@ __global__ __launch_bounds__(256) void gram128_kernel(GramArgs a) {
   constexpr int NV = KB * VPR / 256;              // vectors per thread per panel and chunk
   __shared__ __attribute__((aligned(16))) L lds[2][2][KB * LS];   // [buffer][panel I/J]
 
-  const int bid = blockIdx.y;
+  // XCD-aware order: an XCD takes consecutive tiles of the lower triangle, which
+  // share their row and column panels
+  const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bid = lin / gridDim.x;
   const int part = bid / a.M, blk = bid - part * a.M;
   const int c0 = a.col_off[blk];
   const int nj = a.col_off[blk + 1] - c0;
   const int T_ = (nj + 127) / 128;
   int ti, tj;
-  tri_tile(blockIdx.x, &ti, &tj);
+  tri_tile(lin - bid * gridDim.x, &ti, &tj);
   if (ti >= T_) return;
   const int64_t r0 = a.row_off[part];
   const int64_t m = a.row_off[part + 1] - r0;

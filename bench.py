@@ -271,6 +271,96 @@ def precision_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# End-to-end solve times of Bi-cADMM in the paper's Table 1 (sparse least squares,
+# 4 nodes sharing one RTX 4070 GPU with an i7-13700 host; PyTorch + mpi4py), in
+# seconds, keyed by (s_l, total rows m, features n).  Context, not a target: other
+# hardware, and the paper does not state its precision, parameters or stopping rule.
+PAPER_TABLE1_S = {
+    (0.6, 100000, 2000): 1.1, (0.6, 100000, 4000): 1.8,
+    (0.6, 200000, 2000): 1.7, (0.6, 200000, 4000): 3.0,
+    (0.6, 300000, 2000): 2.2, (0.6, 300000, 4000): 4.0,
+    (0.9, 100000, 2000): 1.1, (0.9, 100000, 4000): 1.9,
+    (0.9, 200000, 2000): 1.7, (0.9, 200000, 4000): 2.9,
+    (0.9, 300000, 2000): 2.2, (0.9, 300000, 4000): 4.1,
+}
+
+
+def paper_shapes_bench(args):
+    """The shapes of the paper's Table 1 solved end to end on one GPU: sparse least
+    squares on N = 4 sample partitions of m/4 rows, m in {1e5, 2e5, 3e5}, n in
+    {2,000, 4,000}, kappa = round(n (1 - s_l)) for sparsity levels s_l in {0.6, 0.9};
+    A iid N(0,1) with unit-norm columns per partition (FP32), a planted model with
+    kappa nonzeros of values +-U(1,2), noise 0.05.  One feature block per partition
+    (the paper's nodes share one GPU), gamma = 10, rho_c = rho_l = 1, rho_b = 0.5,
+    K_in = 5, stopping when p_r, d_r and b_r are all below 1e-4 (checked every 10
+    outer iterations) or after 500.  Timed: Gram, factorisation and iterations with
+    the data already in HBM ("solve"), and separately the host-to-device copy."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    N, seed, noise = 4, 5, 0.05
+    rows_out = []
+    total_solve = 0.0
+    for n in (2000, 4000):
+        for m in (100000, 200000, 300000):
+            mp = m // N
+            models = {}
+            for sl in (0.6, 0.9):
+                kappa = int(round(n * (1 - sl)))
+                models[sl] = (kappa,) + datagen.linear_model(seed + int(10 * sl), n, kappa)
+            probs = {}
+            copy_s = {}
+            for sl, (kappa, supp, val) in models.items():
+                probs[sl] = bca.Problem("squared", n, [mp] * N, 1, kappa, gamma=10.0, rho_c=1.0,
+                                        rho_b=0.5, rho_l=1.0, inner_iters=5, max_iters=500,
+                                        dtype="f32", tol=(1e-4, 1e-4, 1e-4), check_every=10)
+                copy_s[sl] = 0.0
+            for i in range(N):
+                k6, s6, v6 = models[0.6]
+                A, b6 = datagen.linear_partition(seed, i, mp, n, s6, v6, noise, "f32", True)
+                k9, s9, v9 = models[0.9]
+                b9 = datagen.linear_targets(seed, i, A, s9, v9, noise)
+                for sl, b in ((0.6, b6), (0.9, b9)):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    probs[sl].set_data(i, A, b)
+                    torch.cuda.synchronize()
+                    copy_s[sl] += time.perf_counter() - t
+                del A, b6, b9
+            for sl, (kappa, supp, val) in models.items():
+                P = probs[sl]
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                P.finalize()
+                k, conv = P.solve()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+                total_solve += el
+                found = np.intersect1d(P.support(), supp).size
+                paper = PAPER_TABLE1_S[(sl, m, n)]
+                log("s_l %.1f m %d n %d kappa %d: %.3f s (%d iterations, converged %s), copy %.3f s, "
+                    "planted support found %d/%d; paper %.1f s" % (sl, m, n, kappa, el, k, conv,
+                                                                    copy_s[sl], found, kappa, paper))
+                rows_out.append({"s_l": sl, "m": m, "n": n, "kappa": kappa, "solve_s": el,
+                                 "iterations": k, "converged": conv, "copy_s": copy_s[sl],
+                                 "planted_found": int(found), "paper_s": paper,
+                                 "paper_over_ours": paper / el})
+                P.close()
+    ratios = [r["paper_over_ours"] for r in rows_out]
+    out = {"metric": "end-to-end solve time at the paper's Table 1 shapes (context)",
+           "value": total_solve, "unit": "s", "n_gpus": 1, "steps": len(rows_out), "warmup": 0,
+           "ms_per_step": total_solve / len(rows_out) * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sls_table1_shapes_4_partitions", "N": N, "M": 1,
+                      "m": [100000, 200000, 300000], "n": [2000, 4000], "s_l": [0.6, 0.9],
+                      "tol": 1e-4, "max_iters": 500, "inner_iters": 5},
+           "paper_hardware": "RTX 4070 (12 GB) + i7-13700; PyTorch 2.3 + mpi4py",
+           "geomean_paper_over_ours": float(np.exp(np.mean(np.log(ratios)))),
+           "cases": rows_out}
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Continuous batching on a Poisson trace versus the plain one-at-a-time method
     on the same trace.  Requests: 80% sparse-fit problems of the batched size
@@ -380,10 +470,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve", "precision"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve", "precision",
+                                                         "paper-shapes"],
                     help="plain: one problem (default); batched: many uneven problems in one "
                          "persistent launch; serve: continuous batching on a Poisson trace; precision: "
-                         "BF16 beside FP32 at 16 x 100,000 x 10,000")
+                         "BF16 beside FP32 at 16 x 100,000 x 10,000; paper-shapes: the sparse least-squares "
+                         "shapes of the paper's Table 1, end to end")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
@@ -391,8 +483,8 @@ def main():
                     help="precision: rows per partition (default 100,000; smaller values shrink n too)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the partitions of this build live in one GPU's "
-              "memory and no multi-GPU path exists (requested --gpus %d)" % args.gpus,
+        print("bench.py runs on one GPU only: all partitions live in one GPU's memory and "
+              "there is no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
@@ -416,6 +508,8 @@ def main():
         return serve_bench(args)
     if args.mode == "precision":
         return precision_bench(args)
+    if args.mode == "paper-shapes":
+        return paper_shapes_bench(args)
 
     t = time.perf_counter()
     w = workload(args.workload)

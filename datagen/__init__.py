@@ -239,6 +239,13 @@ def linear_partition(seed: int, i: int, m: int, n: int, supp, val, noise: float,
     return Ai, b
 
 
+def linear_targets(seed: int, i: int, A: np.ndarray, supp, val, noise: float) -> np.ndarray:
+    """b_i = A_i x* + N(0, noise^2) for partition i of the sparse linear recipe, from
+    an already drawn (canonical) A_i: the same targets linear_partition returns,
+    for another planted model on the same matrix."""
+    return sparse_predict(A, supp, val) + noise * normal_vector(seed, S_NOISE + i, A.shape[0])
+
+
 def linear_workload(seed: int, N: int, m_per, n: int, kappa: int, k_true: int, noise: float,
                     n_blocks: int, dtype: str = "f64", normalize: bool = False,
                     max_iters: int = 200, inner_iters: int = 5, rho: float = 1.0,

@@ -176,6 +176,26 @@ def test_logistic_f32_parity_small():
     P.close()
 
 
+def test_table1_recipe_dense_support_parity():
+    """The recipe of the paper's Table 1 shapes (unit-norm columns per partition,
+    kappa = 0.4 n with a planted model of that many nonzeros) at a size the oracle
+    finishes in seconds: FP32, one feature block (n_j = 200: four 64-wide tiles of the
+    cached inverse, the last one ragged), a top-kappa that keeps 40 % of the entries."""
+    w = datagen.linear_workload(5, N=4, m_per=[500, 500, 500, 500], n=200, kappa=80, k_true=80,
+                                noise=0.05, n_blocks=1, dtype="f32", normalize=True, max_iters=30)
+    P = make_gpu(w)
+    P.step(w.max_iters)
+    o = make_oracle(w)
+    o.iterate(w.max_iters, w.inner_iters)
+    assert o.topk_margin() > 1e-4
+    assert np.array_equal(P.support(), o.support())
+    assert np.array_equal(P.support(), np.nonzero(w.x_true)[0])
+    assert rel(P.coef(), o.coef()) < 1e-5
+    f, fo = P.objective(), o.objective(o.coef())
+    assert abs(f - fo) <= 1e-5 * abs(fo)
+    P.close()
+
+
 def test_squared_f32_device_input_matches_host_input():
     w = datagen.linear_workload(41, N=2, m_per=[400, 377], n=130, kappa=6, k_true=6, noise=0.05,
                                 n_blocks=3, dtype="f32", max_iters=20)

@@ -32,7 +32,9 @@ Readings where the paper is silent or inconsistent:
   - all state starts at zero; a fixed number K_in of warm-started inner
     iterations per outer iteration; rho_l as given by the caller;
   - losses: squared sum (q - b)^2 (no 1/2, as in the experimental SLS problem),
-    logistic sum log(1 + exp(-b q)), softmax sum LSE(Q_k) - Q_{k, y_k};
+    logistic sum log(1 + exp(-b q)), softmax sum LSE(Q_k) - Q_{k, y_k}, and for
+    the sparse SVM the paper names without a formulation the hinge loss
+    sum max(0, 1 - b q), b in {-1, +1}, with the same ridge term;
   - softmax sparsity is row sparsity: Hempel applied to the row norms of X.
 """
 from __future__ import annotations
@@ -45,7 +47,7 @@ import numpy as np
 from scipy.linalg import cholesky, solve_triangular
 from scipy.special import expit, logsumexp, softmax as _softmax
 
-LOSS_SQUARED, LOSS_LOGISTIC, LOSS_SOFTMAX = 0, 1, 2
+LOSS_SQUARED, LOSS_LOGISTIC, LOSS_SOFTMAX, LOSS_HINGE = 0, 1, 2, 3
 
 
 def split_columns(n: int, M: int):
@@ -67,6 +69,8 @@ def loss_value(loss: int, q: np.ndarray, b: np.ndarray) -> float:
         return float(np.sum((q - b) ** 2))
     if loss == LOSS_LOGISTIC:
         return float(np.sum(np.logaddexp(0.0, -b * q)))
+    if loss == LOSS_HINGE:
+        return float(np.sum(np.maximum(0.0, 1.0 - b * q)))
     rows = np.arange(q.shape[0])
     return float(np.sum(logsumexp(q, axis=1) - q[rows, b.astype(np.int64)]))
 
@@ -115,6 +119,19 @@ def prox_logistic(c: np.ndarray, b: np.ndarray, M: int, rho_l: float,
         if not active.any():
             break
     return q / M
+
+
+def prox_hinge(c: np.ndarray, b: np.ndarray, M: int, rho_l: float) -> np.ndarray:
+    """Hinge loss max(0, 1 - b q), b in {-1, +1}.  With s = b q and d = b M c
+    (b^2 = 1) the problem is max(0, 1 - s) + (beta/2)(s - d)^2, whose minimiser is
+      s = d            if d >= 1           (loss inactive at the quadratic's minimum),
+      s = d + 1/beta   if d + 1/beta <= 1  (on the linear piece: -1 + beta (s - d) = 0),
+      s = 1            otherwise           (at the kink);
+    q = b s and w = q / M."""
+    beta = rho_l / M
+    d = b * M * np.asarray(c, dtype=np.float64)
+    s = np.where(d >= 1.0, d, np.where(d + 1.0 / beta <= 1.0, d + 1.0 / beta, 1.0))
+    return b * s / M
 
 
 def prox_softmax(c: np.ndarray, y: np.ndarray, M: int, rho_l: float,
@@ -172,6 +189,8 @@ def omega_prox(loss: int, c, b, M, rho_l):
         return prox_squared(c, b, M, rho_l)
     if loss == LOSS_LOGISTIC:
         return prox_logistic(c, b, M, rho_l)
+    if loss == LOSS_HINGE:
+        return prox_hinge(c, b, M, rho_l)
     return prox_softmax(c, b, M, rho_l)
 
 

@@ -17,7 +17,7 @@ from scipy.optimize import brentq, linprog, minimize
 
 import datagen
 import oracle
-from oracle.bicadmm import LOSS_LOGISTIC, LOSS_SOFTMAX, LOSS_SQUARED
+from oracle.bicadmm import LOSS_HINGE, LOSS_LOGISTIC, LOSS_SOFTMAX, LOSS_SQUARED
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -121,6 +121,33 @@ def test_prox_logistic_matches_brent_root():
         f = lambda q: -b[k] / (1 + math.exp(b[k] * q)) + beta * (q - M * c[k])
         q = brentq(f, M * c[k] - 1 / beta - 1, M * c[k] + 1 / beta + 1, xtol=1e-15, rtol=1e-15)
         assert abs(w[k] * M - q) <= 1e-12 * max(1.0, abs(q))
+
+
+def test_prox_hinge_is_the_minimiser():
+    """The closed-form hinge prox against a bounded scalar minimiser and a dense
+    grid of the per-sample objective max(0, 1 - b q) + (beta/2)(q - Mc)^2, over
+    inputs that reach all three branches (loss inactive, linear piece, kink)."""
+    from scipy.optimize import minimize_scalar
+    r = _rng(23)
+    seen = set()
+    for M in (1, 2, 4):
+        for rho in (0.3, 1.0, 5.0):
+            beta = rho / M
+            c = r.uniform(-3.0, 3.0, 40) / M
+            b = np.where(r.random(40) < 0.5, -1.0, 1.0)
+            w = oracle.prox_hinge(c, b, M, rho)
+            for k in range(40):
+                f = lambda q: max(0.0, 1.0 - b[k] * q) + 0.5 * beta * (q - M * c[k]) ** 2
+                lo, hi = M * c[k] - 2.0 / beta - 2.0, M * c[k] + 2.0 / beta + 2.0
+                ref = minimize_scalar(f, bounds=(lo, hi), method="bounded",
+                                      options=dict(xatol=1e-12)).x
+                grid = np.linspace(lo, hi, 20001)
+                fq = f(M * w[k])
+                assert fq <= min(f(q) for q in grid) + 1e-12
+                assert abs(M * w[k] - ref) < 1e-6
+                d = b[k] * M * c[k]
+                seen.add(0 if d >= 1 else (1 if d + 1 / beta <= 1 else 2))
+    assert seen == {0, 1, 2}
 
 
 def test_prox_softmax_matches_generic_minimiser():
@@ -326,6 +353,43 @@ def test_kappa_equal_n_softmax_gives_regularised_mle():
     res = minimize(f, np.zeros(n * C), jac=g, method="BFGS", options=dict(gtol=1e-12))
     Z = o.state.z
     assert np.linalg.norm(Z.ravel() - res.x) / np.linalg.norm(res.x) < 1e-6
+
+
+def test_kappa_equal_n_hinge_gives_regularised_svm():
+    """Hinge loss (the sparse SVM) with kappa = n: Bi-cADMM converges to the
+    L2-regularised SVM, min sum max(0, 1 - b a^T x) + ||x||^2 / (2 gamma), here
+    the QP in (x, xi) solved by SLSQP; and its KKT conditions hold: x / gamma =
+    sum_k alpha_k b_k a_k with alpha_k = 1 inside the margin, 0 outside it, and
+    alpha_k in [0, 1] on it."""
+    N, m, n, gam = 2, 30, 5, 2.0
+    r = _rng(12)
+    A = [r.standard_normal((m, n)) for _ in range(N)]
+    xt = r.standard_normal(n)
+    b = [np.where(Ai @ xt + 0.5 * r.standard_normal(m) >= 0, 1.0, -1.0) for Ai in A]
+    o = oracle.BiCADMM(A, b, LOSS_HINGE, 2, n, gam, 2.0, 1.0, 2.0)
+    o.iterate(1200, 5)
+    z = o.state.z
+    Aall, ball = np.vstack(A), np.concatenate(b)
+    K = len(ball)
+    f = lambda v: np.sum(v[n:]) + v[:n] @ v[:n] / (2 * gam)
+    g = lambda v: np.concatenate([v[:n] / gam, np.ones(K)])
+    cons = [{"type": "ineq", "fun": lambda v: v[n:],
+             "jac": lambda v: np.hstack([np.zeros((K, n)), np.eye(K)])},
+            {"type": "ineq", "fun": lambda v: v[n:] - (1 - ball * (Aall @ v[:n])),
+             "jac": lambda v: np.hstack([ball[:, None] * Aall, np.eye(K)])}]
+    v0 = np.concatenate([np.zeros(n), np.ones(K)])
+    res = minimize(f, v0, jac=g, constraints=cons, method="SLSQP", options=dict(ftol=1e-15, maxiter=1000))
+    assert np.linalg.norm(z - res.x[:n]) / np.linalg.norm(res.x[:n]) < 1e-7
+    fz = np.sum(np.maximum(0.0, 1.0 - ball * (Aall @ z))) + z @ z / (2 * gam)
+    assert abs(fz - f(res.x)) <= 1e-9 * fz
+    # KKT
+    mar = ball * (Aall @ z)
+    inside, onm = mar < 1 - 1e-8, np.abs(mar - 1) <= 1e-8
+    rest = z / gam - (ball[inside, None] * Aall[inside]).sum(axis=0)
+    B = (ball[onm, None] * Aall[onm]).T
+    alpha = np.linalg.lstsq(B, rest, rcond=None)[0]
+    assert np.linalg.norm(B @ alpha - rest) <= 1e-7 * max(1.0, np.linalg.norm(z / gam))
+    assert np.all(alpha >= -1e-7) and np.all(alpha <= 1 + 1e-7)
 
 
 # ------------------------------------------------------------------ P8

@@ -77,6 +77,10 @@ def workload(name):
         return datagen.linear_workload(1, N=8, m_per=50000, n=5000, kappa=50, k_true=50,
                                        noise=0.1, n_blocks=4, dtype="f32", max_iters=100,
                                        name=name)
+    if name == "ssvm_8x50000x5000_f32":
+        # the same shape, sparse SVM (hinge loss) on the sparse linear recipe's rows
+        return datagen.svm_workload(1, N=8, m_per=50000, n=5000, kappa=50, k_true=50,
+                                    n_blocks=4, dtype="f32", max_iters=100, name=name)
     raise SystemExit("unknown workload " + name)
 
 
@@ -514,7 +518,7 @@ def main():
     t = time.perf_counter()
     w = workload(args.workload)
     log("generated %s in %.1f s" % (w.name, time.perf_counter() - t))
-    loss = {0: "squared", 1: "logistic"}[w.loss]
+    loss = {0: "squared", 1: "logistic", 3: "hinge"}[w.loss]
     total_iters = args.warmup + args.steps
     P = bca.Problem(loss, w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
                     rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,

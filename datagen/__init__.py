@@ -40,7 +40,7 @@ S_SIZES = 0x20        # instance sizes (batched / serving)
 S_ARRIVAL = 0x21      # serving arrival times
 S_KIND = 0x22         # serving request kinds
 
-LOSS_SQUARED, LOSS_LOGISTIC, LOSS_SOFTMAX = 0, 1, 2
+LOSS_SQUARED, LOSS_LOGISTIC, LOSS_SOFTMAX, LOSS_HINGE = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -300,6 +300,35 @@ def logistic_workload(seed: int, N: int, m_per, n: int, kappa: int, k_true: int,
                     n_blocks=n_blocks, dtype=dtype, x_true=x_true, max_iters=max_iters,
                     inner_iters=inner_iters, rho_c=rho, rho_b=0.5 * rho, rho_l=rho, gamma=gamma,
                     meta=dict(seed=seed, ar=ar))
+
+
+def svm_workload(seed: int, N: int, m_per, n: int, kappa: int, k_true: int, n_blocks: int,
+                 dtype: str = "f32", noise: float = 0.5, max_iters: int = 100,
+                 inner_iters: int = 5, rho: float = 1.0, gamma: float = 10.0,
+                 name: str = "svm") -> Workload:
+    """Sparse SVM (hinge loss): A_i iid N(0,1), planted x* with values +-U(1,2),
+    labels b_k = +1 if a_k^T x* + N(0, noise^2) >= 0 else -1."""
+    rows = m_per if isinstance(m_per, (list, tuple)) else [m_per] * N
+    supp, val = linear_model(seed, n, k_true)
+    x_true = np.zeros(n)
+    x_true[supp] = val
+    A_out, b_out = [], []
+    for i, m in enumerate(rows):
+        G = normal_matrix(seed, S_A + i, m, n)
+        if dtype == "f64":
+            Ai, Aval = G, G
+        else:
+            A32 = to_f32(G)
+            del G
+            Ai = A32 if dtype == "f32" else f32_to_bf16_bits(A32)
+            Aval = A32
+        score = sparse_predict(Aval, supp, val) + noise * normal_vector(seed, S_LABEL + i, m)
+        A_out.append(Ai)
+        b_out.append(np.where(score >= 0, 1.0, -1.0))
+    return Workload(name=name, loss=LOSS_HINGE, A=A_out, b=b_out, n=n, kappa=kappa,
+                    n_blocks=n_blocks, dtype=dtype, x_true=x_true, max_iters=max_iters,
+                    inner_iters=inner_iters, rho_c=rho, rho_b=0.5 * rho, rho_l=rho, gamma=gamma,
+                    meta=dict(seed=seed, noise=noise))
 
 
 def softmax_workload(seed: int, N: int, m_per, n: int, C: int, kappa: int, k_true: int,

@@ -51,12 +51,15 @@ enum {
 };
 
 /* Loss functions l_i (Sec. 2 lists sparse linear, logistic and softmax
- * regression; the experimental section fixes the squared loss without 1/2):
+ * regression; the experimental section fixes the squared loss without 1/2; the
+ * introduction also names sparse SVMs, without a formulation):
  *   SQUARED   l(q; b) = sum_k (q_k - b_k)^2,          b real
  *   LOGISTIC  l(q; b) = sum_k log(1 + exp(-b_k q_k)),  b_k in {-1, +1}
  *   SOFTMAX   l(Q; y) = sum_k LSE(Q_k) - Q_{k, y_k},   y_k in {0..C-1};
- *             the sparsity then counts rows of the n x C coefficient matrix. */
-enum { BCA_LOSS_SQUARED = 0, BCA_LOSS_LOGISTIC = 1, BCA_LOSS_SOFTMAX = 2 };
+ *             the sparsity then counts rows of the n x C coefficient matrix
+ *   HINGE     l(q; b) = sum_k max(0, 1 - b_k q_k),     b_k in {-1, +1}
+ *             (the sparse SVM, with the same ridge term 1/(2 gamma) ||x||^2). */
+enum { BCA_LOSS_SQUARED = 0, BCA_LOSS_LOGISTIC = 1, BCA_LOSS_SOFTMAX = 2, BCA_LOSS_HINGE = 3 };
 
 /* Storage precision of A.  F64: FP64 arithmetic throughout.  F32: FP32
  * products with FP64 long sums.  BF16: BF16 storage, FP32 products, FP64 long

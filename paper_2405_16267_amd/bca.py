@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbca.so")
 BCA_OK = 0
 ERRORS = {-1: "BCA_E_INVALID", -2: "BCA_E_OOM", -3: "BCA_E_STATE", -4: "BCA_E_NONFINITE",
           -5: "BCA_E_DEVICE", -6: "BCA_E_BUDGET", -7: "BCA_E_NOTFOUND", -8: "BCA_E_CANCELLED"}
-LOSS = {"squared": 0, "logistic": 1, "softmax": 2}
+LOSS = {"squared": 0, "logistic": 1, "softmax": 2, "hinge": 3}
 DTYPE = {"f64": 0, "f32": 1, "bf16": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 VEC_X, VEC_U, VEC_Z, VEC_S, VEC_OMEGA, VEC_NU, VEC_TV = range(7)

@@ -335,7 +335,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (!prm || !out) return fail(BCA_E_INVALID, "null argument");
   *out = nullptr;
   const bca_params& p = *prm;
-  if (p.loss < 0 || p.loss > 2) return fail(BCA_E_INVALID, "unknown loss %d", p.loss);
+  if (p.loss < 0 || p.loss > 3) return fail(BCA_E_INVALID, "unknown loss %d", p.loss);
   const int C = p.loss == BCA_LOSS_SOFTMAX ? p.n_classes : 1;
   if (p.loss != BCA_LOSS_SOFTMAX && p.n_classes != 1 && p.n_classes != 0)
     return fail(BCA_E_INVALID, "n_classes must be 1 for this loss");
@@ -510,7 +510,7 @@ int bca_set_data(bca_problem P, int32_t part, const void* A, int64_t ld, const v
   TRY(launch_ok(launch_check(dstA, P->dtype, m * P->ld, P->status + 1, P->stream), "check"));
   if (!softmax)
     TRY(launch_ok(launch_check(P->b + P->row_off[part], BCA_F64, m, P->status + 1, P->stream), "check"));
-  if (P->p.loss == BCA_LOSS_LOGISTIC)
+  if (P->p.loss == BCA_LOSS_LOGISTIC || P->p.loss == BCA_LOSS_HINGE)
     TRY(launch_ok(launch_check_signs(P->b + P->row_off[part], m, P->status + 2, P->stream), "check"));
   if (softmax)
     TRY(launch_ok(launch_check_labels(P->y + P->row_off[part], m, P->C, P->status + 2, P->stream), "check"));

@@ -10,6 +10,16 @@ namespace bca {
 // w_prev (the previous omega-bar of the sample) only seeds the Newton iteration.
 __device__ __forceinline__ double prox_scalar(int loss, double c, double b, int M, double rho_l, double w_prev) {
   if (loss == BCA_LOSS_SQUARED) return (2.0 * b + rho_l * c) / (2.0 * M + rho_l);
+  if (loss == BCA_LOSS_HINGE) {
+    // Hinge max(0, 1 - b q), b = +-1: with s = b q and d = b M c the problem is
+    // max(0, 1 - s) + (beta/2)(s - d)^2, minimised at s = d when d >= 1 (loss
+    // inactive), at s = d + 1/beta when that is <= 1 (linear piece), else at the
+    // kink s = 1.
+    const double ib = 1.0 / (rho_l / M);  // 1 / beta
+    const double d = b * M * c;
+    const double s = d >= 1.0 ? d : (d + ib <= 1.0 ? d + ib : 1.0);
+    return b * s / M;
+  }
   // Logistic: root of -b sigmoid(-b q) + beta (q - Mc), bracketed in
   // [Mc - 1/beta, Mc + 1/beta]; Newton steps kept inside the bracket by bisection,
   // until the step is below the rounding level of the derivative, a few ulp of

@@ -232,6 +232,8 @@ __global__ __launch_bounds__(NT) void objective_kernel(ObjArgs a) {
       const double b = a.b[r0 + row];
       if (a.loss == BCA_LOSS_SQUARED) {
         lsum += (qv - b) * (qv - b);
+      } else if (a.loss == BCA_LOSS_HINGE) {
+        lsum += fmax(0.0, 1.0 - b * qv);
       } else {
         const double t = -b * qv;  // log(1 + exp(t)), overflow-safe
         lsum += t > 0 ? t + log1p(exp(-t)) : log1p(exp(t));

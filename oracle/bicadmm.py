@@ -44,7 +44,7 @@ from dataclasses import dataclass, field
 from typing import List, Optional
 
 import numpy as np
-from scipy.linalg import cholesky, solve_triangular
+from scipy.linalg import cho_factor, cho_solve, cholesky, solve_triangular
 from scipy.special import expit, logsumexp, softmax as _softmax
 
 LOSS_SQUARED, LOSS_LOGISTIC, LOSS_SOFTMAX, LOSS_HINGE = 0, 1, 2, 3
@@ -287,9 +287,13 @@ class BiCADMM:
 
     def __init__(self, A_parts, b_parts, loss: int, n_blocks: int, kappa: int, gamma: float,
                  rho_c: float, rho_b: float, rho_l: float, n_classes: int = 1,
-                 n_partitions: Optional[int] = None):
+                 n_partitions: Optional[int] = None, exact_x: bool = False):
         """n_partitions: the problem's N when only some partitions' data are given
-        (x-updates are then run for those partitions only)."""
+        (x-updates are then run for those partitions only).  exact_x (squared loss
+        only): the x-update of every partition is its exact minimiser, the limit of
+        Algorithm 2's inner loop, instead of K_in inner iterations."""
+        if exact_x and loss != LOSS_SQUARED:
+            raise ValueError("the exact x-update is the closed form of the squared loss")
         self.A = [np.asarray(A, dtype=np.float64) for A in A_parts]
         self.b = [np.asarray(b) for b in b_parts]
         self.loss = loss
@@ -312,6 +316,13 @@ class BiCADMM:
                 K = rho_l * G + shift * np.eye(c1 - c0)
                 Li.append(cholesky(K, lower=True))
             self.L.append(Li)
+        # Exact x-update of partition i (squared loss): the minimiser of
+        # ||A_i x - b_i||^2 + ||x||^2 / (2 N gamma) + (rho_c/2)||x - z + u_i||^2 solves
+        # H_i x = 2 A_i^T b_i + rho_c (z - u_i),  H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I.
+        self.exact_x = exact_x
+        if exact_x:
+            self.H = [cho_factor(2.0 * A.T @ A + shift * np.eye(self.n), lower=True) for A in self.A]
+            self.c = [2.0 * A.T @ b for A, b in zip(self.A, self.b)]
         self.state = self.zero_state()
 
     # -- state
@@ -354,6 +365,10 @@ class BiCADMM:
             st.nu[i] = st.nu[i] + a - st.omega[i]            # nu-update
         st.x[i] = x_i
 
+    def x_update_exact(self, i: int, st: Optional[State] = None):
+        st = self.state if st is None else st
+        st.x[i] = cho_solve(self.H[i], self.c[i] + self.rho_c * (st.z - st.u[i]))
+
     def _row_norms(self, X):
         return X if self.C == 1 else np.sqrt(np.sum(X * X, axis=1))
 
@@ -389,7 +404,10 @@ class BiCADMM:
         st = self.state if st is None else st
         for _ in range(outer_iters):
             for i in range(self.N):
-                self.x_update(i, inner_iters, st)
+                if self.exact_x:
+                    self.x_update_exact(i, st)
+                else:
+                    self.x_update(i, inner_iters, st)
             self.global_update(st)
         return st
 

@@ -392,6 +392,34 @@ def test_kappa_equal_n_hinge_gives_regularised_svm():
     assert np.all(alpha >= -1e-7) and np.all(alpha <= 1 + 1e-7)
 
 
+def test_exact_x_update_is_the_limit_of_algorithm_2():
+    """The exact x-update (squared loss) is what Algorithm 2's inner loop converges
+    to: with 200 warm-started inner iterations per outer iteration the two runs
+    agree to rounding over several outer iterations, with 50 they do not yet."""
+    N, m, n = 3, 40, 12
+    A, b = _problem(3, N, m, n)
+    args = (A, b, LOSS_SQUARED, 2, 4, 10.0, 1.0, 0.5, 1.0)
+    oe = oracle.BiCADMM(*args, exact_x=True)
+    oa = oracle.BiCADMM(*args)
+    oa50 = oracle.BiCADMM(*args)
+    for _ in range(3):
+        oe.iterate(1, 5)
+        oa.iterate(1, 200)
+        oa50.iterate(1, 50)
+        for i in range(N):
+            assert np.linalg.norm(oa.state.x[i] - oe.state.x[i]) <= 1e-13 * np.linalg.norm(oe.state.x[i])
+        assert np.linalg.norm(oa.state.z - oe.state.z) <= 1e-13 * np.linalg.norm(oe.state.z)
+    assert np.linalg.norm(oa50.state.z - oe.state.z) > 1e-10 * np.linalg.norm(oe.state.z)
+    # kappa = n: the exact variant reaches the global ridge solution as well
+    o = oracle.BiCADMM(A, b, LOSS_SQUARED, 1, n, 10.0, 5.0, 2.5, 5.0, exact_x=True)
+    o.iterate(1500, 5)
+    S = sum(Ai.T @ Ai for Ai in A)
+    x = np.linalg.solve(2 * S + np.eye(n) / 10.0, 2 * sum(Ai.T @ bi for Ai, bi in zip(A, b)))
+    assert np.linalg.norm(o.state.z - x) / np.linalg.norm(x) < 1e-10
+    with pytest.raises(ValueError):
+        oracle.BiCADMM(A, [np.sign(bi) for bi in b], LOSS_LOGISTIC, 1, 4, 10.0, 1.0, 0.5, 1.0, exact_x=True)
+
+
 # ------------------------------------------------------------------ P8
 def test_orthogonal_design_closed_form():
     """sum A_i^T A_i = I and squared loss: the l0-constrained optimum is hard

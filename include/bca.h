@@ -88,8 +88,18 @@ typedef struct {
   double tol_p, tol_d, tol_b;          /* bca_solve stops when p_r <= tol_p, d_r <= tol_d, b_r <= tol_b */
   int32_t a_dtype;       /* BCA_F64 / BCA_F32 / BCA_BF16 */
   int32_t check_every;   /* bca_solve reads the residuals back every this many iterations (0 = 10) */
-  uint32_t flags;        /* reserved, must be 0 */
+  uint32_t flags;        /* BCA_FLAG_* bits, 0 for the paper's method as written */
 } bca_params;
+
+/* Variant of the x-update (Sec. 3.1).  EXACT_X, squared loss only: the x-update
+ * of every partition is solved exactly, x_i = H_i^-1 (2 A_i^T b_i + rho_c (z -
+ * u_i)) with H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I, i.e. the limit of
+ * Algorithm 2's inner loop, instead of inner_iters warm-started inner iterations.
+ * H_i^-1 is formed once at finalize (n x n per partition, FP64) and A_i^T b_i is
+ * streamed once, so an outer iteration reads no A at all; n_blocks is then
+ * ignored (one block of n features) and the omega-bar / nu state stays zero.
+ * Not available in the batched and serving forms. */
+enum { BCA_FLAG_EXACT_X = 1 };
 
 /* Create a problem: validates the parameters and allocates device memory for
  * the data and the ADMM state.  hip_stream is a hipStream_t (may be NULL).
@@ -248,10 +258,11 @@ enum { BCA_REQ_QUEUED = 0, BCA_REQ_RUNNING = 1, BCA_REQ_DONE = 2, BCA_REQ_FAILED
 int bca_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t round_iters, void* hip_stream,
                       bca_server* out);
 
-/* Queue a request: params as for bca_create (params->rows read here), A[i] and
- * b[i] host pointers of partition i laid out as for bca_set_data with ld = n;
- * both are copied before the call returns.  *ticket identifies the request.
- * Errors: BCA_E_INVALID, BCA_E_BUDGET (the request alone exceeds the budget). */
+/* Queue a request: params as for bca_create (params->rows read here; flags 0),
+ * A[i] and b[i] host pointers of partition i laid out as for bca_set_data with
+ * ld = n; both are copied before the call returns.  *ticket identifies the
+ * request.  Errors: BCA_E_INVALID, BCA_E_BUDGET (the request alone exceeds the
+ * budget). */
 int bca_server_submit(bca_server s, const bca_params* params, const void* const* A, const void* const* b,
                       uint64_t* ticket);
 

@@ -12,6 +12,7 @@
 //   kinv                      P_ij = K_ij^-1 as 64 x 64 tiles of its lower block triangle
 //                             (sum_ij T_ij (T_ij + 1) / 2 tiles, T_ij = ceil(n_j / 64))
 //   ypart                     N M x tmax x tmax x 64 doubles: slots of the symmetric product
+//   atb                       exact x-update only: N x n doubles, 2 A_i^T b_i
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,6 +92,8 @@ struct bca_problem_s {
   // host state
   std::vector<char> loaded;
   bool finalized = false;
+  bool exact = false;        // BCA_FLAG_EXACT_X: exact x-update, one block
+  double* atb = nullptr;
   bool need_prime = false;
   int iter = 0;
   bool timing = false;
@@ -249,6 +252,7 @@ SolveArgs solve_args(bca_problem P) {
   a.rhs = P->rhs;
   a.ypart = P->ypart;
   a.kinv = P->kinv;
+  a.atb = P->atb;
   a.fac_off = P->d_fac_off;
   a.col_off = P->d_col_off;
   a.N = P->N;
@@ -289,6 +293,10 @@ int launch_ok(hipError_t e, const char* what) {
 }
 
 int prime(bca_problem P) {
+  if (P->exact) {  // no inner loop: nothing to re-derive from the state
+    P->need_prime = false;
+    return BCA_OK;
+  }
   TRY(launch_ok(launch_make_xs(P->x, P->xs, xs_is_f64(P), P->N, P->n, P->C, P->ld, P->stream), "make_xs"));
   Timer t(P, BCA_KC_STREAM);
   TRY(launch_ok(launch_stream(stream_args(P, 1), P->dtype, P->stream), "stream(prime)"));
@@ -298,6 +306,18 @@ int prime(bca_problem P) {
 
 int one_outer(bca_problem P) {
   const SolveArgs sa = solve_args(P);
+  if (P->exact) {
+    {
+      Timer t(P, BCA_KC_SOLVE);
+      TRY(launch_ok(launch_solve_exact(sa, P->stream), "solve(exact)"));
+    }
+    {
+      Timer t(P, BCA_KC_GLOBAL);
+      TRY(launch_ok(launch_global(global_args(P), P->stream), "global"));
+    }
+    P->iter += 1;
+    return BCA_OK;
+  }
   const StreamArgs st = stream_args(P, 0);
   for (int k = 0; k < P->p.inner_iters; ++k) {
     {
@@ -350,7 +370,9 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     return fail(BCA_E_INVALID, "gamma, rho_c, rho_b, rho_l must be > 0");
   if (p.inner_iters < 1 || p.max_iters < 1) return fail(BCA_E_INVALID, "inner_iters and max_iters must be >= 1");
   if (p.a_dtype < 0 || p.a_dtype > 2) return fail(BCA_E_INVALID, "unknown a_dtype %d", p.a_dtype);
-  if (p.flags != 0) return fail(BCA_E_INVALID, "flags must be 0");
+  if (p.flags & ~(uint32_t)BCA_FLAG_EXACT_X) return fail(BCA_E_INVALID, "unknown flags 0x%x", p.flags);
+  if ((p.flags & BCA_FLAG_EXACT_X) && p.loss != BCA_LOSS_SQUARED)
+    return fail(BCA_E_INVALID, "the exact x-update needs the squared loss");
   for (int i = 0; i < p.n_partitions; ++i)
     if (p.rows[i] < 1) return fail(BCA_E_INVALID, "rows[%d] must be >= 1", i);
 
@@ -361,7 +383,8 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   P->n = p.n_features;
   P->C = C;
   P->N = p.n_partitions;
-  P->M = p.n_blocks;
+  P->exact = (p.flags & BCA_FLAG_EXACT_X) != 0;
+  P->M = P->exact ? 1 : p.n_blocks;   // the exact x-update factors all n features at once
   P->kappa = p.kappa;
   P->dtype = p.a_dtype;
   P->ld = ((int64_t)P->n + 63) / 64 * 64;
@@ -455,6 +478,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->status, 4));
   if (rc == BCA_OK) chk(dalloc(P, &P->gpart, (size_t)P->N * P->Gp * P->ld * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->kinv, (size_t)P->fac_total));
+  if (rc == BCA_OK && P->exact) chk(dalloc(P, &P->atb, (size_t)P->N * P->n));
   if (rc == BCA_OK) chk(dalloc(P, &P->objpart, (size_t)P->N * P->Gp));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_row_off, P->N + 1));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_col_off, P->M + 1));
@@ -555,7 +579,8 @@ int bca_finalize(bca_problem P) {
   g.N = P->N;
   g.M = P->M;
   g.tiles_max = (P->nj_max + 63) / 64;
-  g.rho_l = P->p.rho_l;
+  // the exact x-update factors H_i = 2 A_i^T A_i + shift I (the squared loss's Hessian)
+  g.rho_l = P->exact ? 2.0 : P->p.rho_l;
   g.shift = P->shift;
   FactorArgs f{};
   f.kbuf = kbuf;
@@ -593,6 +618,24 @@ int bca_finalize(bca_problem P) {
   if (e == hipSuccess)
     e = hipMemsetAsync(P->gpart, 0, (size_t)P->N * P->Gp * P->ld * P->C * sizeof(double), s);
   if (e == hipSuccess) e = hipMemsetAsync(P->support, 0, (size_t)P->kappa * sizeof(int32_t), s);
+  if (e == hipSuccess && P->exact) {
+    // 2 A_i^T b_i, streamed once: the re-derivation pass with omega-bar = b, nu = 0
+    // and x = 0 accumulates sum_k b_k a_k, and the reduction scales it by 2
+    const size_t mb = (size_t)P->m_total * sizeof(double);
+    e = hipMemcpyAsync(P->omega, P->b, mb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_stream(stream_args(P, 1), P->dtype, s);
+    if (e == hipSuccess) {
+      SolveArgs sa = solve_args(P);
+      sa.rhs = P->atb;
+      sa.rho_l = 2.0;
+      sa.rho_c = 0.0;
+      sa.shift = 0.0;
+      e = launch_reduce_rhs(sa, s);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(P->omega, 0, mb, s);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(P->gpart, 0, (size_t)P->N * P->Gp * P->ld * P->C * sizeof(double), s);
+  }
   int st = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&st, P->status, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -944,6 +987,7 @@ int batch_check(bca_problem P) {
   if (!P) return fail(BCA_E_INVALID, "null problem in batch");
   if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
   if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
+  if (P->exact) return fail(BCA_E_INVALID, "the batched form runs Algorithm 2's inner loop (no exact x-update)");
   if (P->dtype == BCA_BF16) return fail(BCA_E_INVALID, "the batched form streams FP32 or FP64 data");
   if (P->nj_max > 1024 || P->nvec > batch_max_nvec())
     return fail(BCA_E_INVALID, "batched problems need n_j <= 1024 and n <= 64*8 vectors per row");
@@ -955,6 +999,7 @@ int batch_check(bca_problem P) {
 int batch_check_basic(bca_problem P) {
   if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
   if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
+  if (P->exact) return fail(BCA_E_INVALID, "the batched form runs Algorithm 2's inner loop (no exact x-update)");
   if (P->dtype == BCA_BF16) return fail(BCA_E_INVALID, "the batched form streams FP32 or FP64 data");
   if (P->nj_max > 1024 || P->nvec > batch_max_nvec())
     return fail(BCA_E_INVALID, "batched problems need n_j <= 1024 and n <= 64*8 vectors per row");

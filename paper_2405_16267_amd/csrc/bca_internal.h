@@ -228,10 +228,15 @@ struct SolveArgs {
   const double* kinv;      // tiled P_ij
   const int64_t* fac_off;  // N*M
   const int32_t* col_off;  // M + 1
+  const double* atb;       // exact x-update: N x n, 2 A_i^T b_i
   int N, M, n, C, nj_max;
   double rho_l, rho_c, shift;
 };
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+// rhs = rho_l sum_w gpart[w] + rho_c (z - u) - shift x only.
+hipError_t launch_reduce_rhs(const SolveArgs& a, hipStream_t s);
+// Exact x-update (squared loss, one block per partition): x = P (atb + rho_c (z - u)).
+hipError_t launch_solve_exact(const SolveArgs& a, hipStream_t s);
 
 struct GlobalArgs {
   double* x;               // N x n x C

@@ -294,6 +294,7 @@ int bca_server_submit(bca_server S, const bca_params* params, const void* const*
   if (!S || !params || !A || !b || !ticket || !params->rows) return BCA_E_INVALID;
   const bca_params& p = *params;
   if (p.n_partitions < 1 || p.n_features < 1) return BCA_E_INVALID;
+  if (p.flags != 0) return BCA_E_INVALID;  // requests run the batched form: no exact x-update
   auto r = std::make_unique<Request>();
   r->params = p;
   r->rows.assign(p.rows, p.rows + p.n_partitions);

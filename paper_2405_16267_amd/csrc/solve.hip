@@ -56,7 +56,9 @@ __global__ __launch_bounds__(256) void symv_kernel(SolveArgs a) {
             nj, a.C, I, J, T, a.ypart + (int64_t)bid * tmax * tmax * PT * a.C);
 }
 
-// one thread per element (i, c) of the block's n_j x C vector
+// one thread per element (i, c) of the block's n_j x C vector; ASSIGN: x = y
+// (the exact x-update) instead of x += y
+template <bool ASSIGN>
 __global__ __launch_bounds__(256) void xupd_kernel(SolveArgs a) {
   const int bid = blockIdx.y;
   const int part = bid / a.M, blk = bid - part * a.M;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(256) void xupd_kernel(SolveArgs a) {
   const int T = (nj + PT - 1) / PT, tmax = (a.nj_max + PT - 1) / PT;
   const double y = symv_gather(a.ypart + (int64_t)bid * tmax * tmax * PT * a.C, i, c, a.C, T);
   const int64_t o = ((int64_t)part * a.n + c0 + i) * a.C + c;
-  const double xn = a.x[o] + y;
+  const double xn = ASSIGN ? y : a.x[o] + y;
   a.xw[o] = xn;
   const int64_t so = (int64_t)part * a.ld * a.C + (int64_t)(c0 + i) * a.C + c;
   if (a.xs_f64)
@@ -85,7 +87,37 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
   hipLaunchKernelGGL(symv_kernel, g2, dim3(256), 0, s, a);
   dim3 g3((unsigned)(((int64_t)a.nj_max * a.C + 255) / 256), a.N * a.M);
-  hipLaunchKernelGGL(xupd_kernel, g3, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(xupd_kernel<false>, g3, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rhs(const SolveArgs& a, hipStream_t s) {
+  if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
+  dim3 g1((unsigned)(((int64_t)a.n * a.C + 255) / 256), a.N);
+  hipLaunchKernelGGL(reduce_rhs_kernel, g1, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Exact x-update of the squared loss: rhs = 2 A_i^T b_i + rho_c (z - u_i) (the
+// first term streamed once at setup), then x = P_i rhs with the same symmetric
+// product as the inner loop's solve.
+__global__ __launch_bounds__(256) void exact_rhs_kernel(SolveArgs a) {
+  const int part = blockIdx.y;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= a.n) return;
+  const int64_t o = (int64_t)part * a.n + k;
+  a.rhs[o] = a.atb[o] + a.rho_c * (a.z[k] - a.u[o]);
+}
+
+hipError_t launch_solve_exact(const SolveArgs& a, hipStream_t s) {
+  if (a.C != 1 || a.M != 1) return hipErrorInvalidValue;
+  dim3 g1((unsigned)((a.n + 255) / 256), a.N);
+  hipLaunchKernelGGL(exact_rhs_kernel, g1, dim3(256), 0, s, a);
+  const int64_t tiles = ptile_count(a.nj_max);
+  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
+  hipLaunchKernelGGL(symv_kernel, g2, dim3(256), 0, s, a);
+  dim3 g3((unsigned)((a.nj_max + 255) / 256), a.N * a.M);
+  hipLaunchKernelGGL(xupd_kernel<true>, g3, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,100 @@
+"""Exact x-update of the squared loss (BCA_FLAG_EXACT_X) against the FP64 oracle's
+exact mode (itself pinned to Algorithm 2's inner-loop limit and the global ridge
+solution): the cached H_i^-1, the state after each outer iteration (FP64, 1e-12),
+a full FP32 run (support exact, coefficients and objective 1e-5), and the
+parameter checks.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _bca():
+    import paper_2405_16267_amd as bca
+    return bca
+
+
+def make(w):
+    bca = _bca()
+    P = bca.Problem("squared", w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
+                    rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=w.max_iters, dtype=w.dtype, exact_x=True)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    return P
+
+
+def make_oracle(w):
+    return oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
+                          w.gamma, w.rho_c, w.rho_b, w.rho_l, exact_x=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def test_exact_inverse_and_state_match_oracle_f64():
+    """n = 300 (five 64-wide tiles, the last ragged) over uneven partitions; the
+    n_blocks = 3 given is ignored by the exact x-update."""
+    bca = _bca()
+    w = datagen.linear_workload(71, N=3, m_per=[420, 390, 351], n=300, kappa=9, k_true=9, noise=0.05,
+                                n_blocks=3, dtype="f64", max_iters=40)
+    P = make(w)
+    shift = 1.0 / (w.N * w.gamma) + w.rho_c
+    for i in range(w.N):
+        A = w.A[i]
+        H = 2.0 * A.T @ A + shift * np.eye(w.n)
+        Kinv = P.inverse(i, 0)
+        assert np.max(np.abs(Kinv @ H - np.eye(w.n))) < 1e-12
+    o = make_oracle(w)
+    for _ in range(3):
+        P.step(1)
+        o.iterate(1, w.inner_iters)
+        for i in range(w.N):
+            assert rel(P.get_vector(bca.VEC_X, i), o.state.x[i]) < 1e-12
+            assert rel(P.get_vector(bca.VEC_U, i), o.state.u[i]) < 1e-12
+        assert rel(P.get_vector(bca.VEC_Z), o.state.z) < 1e-12
+        pr, dr, br, it = P.residuals()
+        opr, odr, obr = o.state.history[-1]
+        assert abs(pr - opr) <= 1e-11 * max(1, opr) and abs(dr - odr) <= 1e-11 * max(1, odr)
+    P.step(w.max_iters - 3)
+    o.iterate(w.max_iters - 3, w.inner_iters)
+    assert o.topk_margin() > 1e-6
+    assert np.array_equal(P.support(), o.support())
+    assert rel(P.coef(), o.coef()) < 1e-11
+    f, fo = P.objective(), o.objective(o.coef())
+    assert abs(f - fo) <= 1e-11 * abs(fo)
+    P.close()
+
+
+def test_exact_f32_parity():
+    w = datagen.linear_workload(72, N=4, m_per=[800, 760, 700, 650], n=530, kappa=10, k_true=10,
+                                noise=0.1, n_blocks=1, dtype="f32", normalize=True, max_iters=30)
+    P = make(w)
+    P.step(w.max_iters)
+    o = make_oracle(w)
+    o.iterate(w.max_iters, w.inner_iters)
+    assert o.topk_margin() > 1e-4
+    assert np.array_equal(P.support(), o.support())
+    assert rel(P.coef(), o.coef()) < 1e-5
+    f, fo = P.objective(), o.objective(o.coef())
+    assert abs(f - fo) <= 1e-5 * abs(fo)
+    P.close()
+
+
+def test_exact_x_parameter_checks():
+    bca = _bca()
+    with pytest.raises(bca.BcaError):
+        bca.Problem("logistic", 20, [50], 1, 3, dtype="f64", exact_x=True)
+    w = datagen.linear_workload(73, N=2, m_per=[60, 55], n=20, kappa=3, k_true=3, noise=0.05,
+                                n_blocks=1, dtype="f64", max_iters=5)
+    P = make(w)
+    with pytest.raises(bca.BcaError):
+        bca.batch_solve([P])
+    P.close()

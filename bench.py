@@ -365,6 +365,235 @@ def paper_shapes_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def paper_sweeps_bench(args):
+    """The remaining experiments of the paper's Sec. 4 run on one GPU (sparse least
+    squares, A iid N(0,1) with unit-norm columns per partition, planted model of
+    kappa = round(n (1 - s_l)) nonzeros of values +-U(1,2), noise 0.05, one feature
+    block per partition, gamma = 10, K_in = 5):
+      rho_b   the convergence study (Fig. 1): n = 4,000, m = 10,000 on N = 4
+              partitions, s_l = 0.8, rho_b in {2, 4, 8, 16} with rho_c = rho_b / 0.5
+              (alpha = 0.5), 200 outer iterations; reported: p_r, d_r, b_r along the run.
+      features  feature scaling (Fig. 2): N in {2, 4, 8} partitions of 800 rows,
+              n from 1,000 to 10,000, s_l = 0.8; each case solved with the default
+              x-step and with the sample-space (Woodbury) x-step.
+      samples   sample scaling (Fig. 3): N in {2, 4, 8}, n = 4,000, s_l = 0.8, rows
+              per partition from 25,000 to 300,000.
+    The scaling runs stop when p_r, d_r and b_r are all below 1e-4 (checked every
+    10 outer iterations) or after 500, with rho_c = rho_l = 1, rho_b = 0.5, and time
+    Gram, factorisation and iterations with the data in HBM.  For the sample
+    scaling the 300,000-row matrices are drawn once per partition and each case
+    takes their leading rows, re-normalised on the device."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    sweeps = ["rho_b", "features", "samples"] if args.sweep == "all" else [args.sweep]
+    out = {"metric": "residual curves and end-to-end solve times of the paper's Sec. 4 "
+                     "experiments (context)",
+           "n_gpus": 1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic", "unit": "s",
+           "config": {"workload": "sls_sec4_sweeps", "sweeps": sweeps, "M": 1,
+                      "inner_iters": 5, "gamma": 10.0, "noise": 0.05}}
+    noise, total = 0.05, 0.0
+
+    def solve_case(P, supp):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P.finalize()
+        k, conv = P.solve()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        return el, k, conv, int(np.intersect1d(P.support(), supp).size)
+
+    if "rho_b" in sweeps:
+        n, m, N, sl = 4000, 10000, 4, 0.8
+        kappa = int(round(n * (1 - sl)))
+        supp, val = datagen.linear_model(21, n, kappa)
+        parts = [datagen.linear_partition(21, i, m // N, n, supp, val, noise, "f32", True)
+                 for i in range(N)]
+        curves = []
+        for rho_b in (2.0, 4.0, 8.0, 16.0):
+            rho_c = rho_b / 0.5
+            K = 200
+            P = bca.Problem("squared", n, [m // N] * N, 1, kappa, gamma=10.0, rho_c=rho_c,
+                            rho_b=rho_b, rho_l=rho_c, inner_iters=5, max_iters=K, dtype="f32")
+            for i, (A, b) in enumerate(parts):
+                P.set_data(i, A, b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            P.finalize()
+            P.step(K)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            total += el
+            h = P.history()
+            found = int(np.intersect1d(P.support(), supp).size)
+            at = [1, 10, 25, 50, 100, 150, 200]
+            pts = {str(k): [float(v) for v in h[k - 1]] for k in at if k <= len(h)}
+            log("rho_b %4.1f rho_c %4.1f: %.3f s for %d iterations; (p_r, d_r, b_r) at 1: %s, "
+                "200: %s; planted support %d/%d" % (rho_b, rho_c, el, len(h), pts.get("1"),
+                                                     pts.get("200"), found, kappa))
+            curves.append({"rho_b": rho_b, "rho_c": rho_c, "seconds": el, "iterations": len(h),
+                           "residuals_p_d_b_at": pts, "planted_found": found, "kappa": kappa})
+            P.close()
+        del parts
+        out["rho_b_sweep"] = {"n": n, "m": m, "N": N, "s_l": sl, "alpha": 0.5, "runs": curves}
+
+    kw = dict(gamma=10.0, rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5, max_iters=500,
+              dtype="f32", tol=(1e-4, 1e-4, 1e-4), check_every=10)
+    if "features" in sweeps:
+        rows_out = []
+        for N in (2, 4, 8):
+            for n in (1000, 2500, 5000, 7500, 10000):
+                kappa = int(round(n * 0.2))
+                supp, val = datagen.linear_model(31, n, kappa)
+                parts = [datagen.linear_partition(31, i, 800, n, supp, val, noise, "f32", True)
+                         for i in range(N)]
+                # the default x-step (n x n inverse per partition) and the sample-space
+                # form (800 x 800 per partition), same iterates up to rounding
+                rec = {"N": N, "m_per": 800, "n": n, "kappa": kappa}
+                for form in ("default", "woodbury"):
+                    P = bca.Problem("squared", n, [800] * N, 1, kappa, woodbury=form == "woodbury",
+                                    **kw)
+                    for i, (A, b) in enumerate(parts):
+                        P.set_data(i, A, b)
+                    el, k, conv, found = solve_case(P, supp)
+                    if form == "default":
+                        total += el
+                    log("features (%s x-step): N %d n %5d kappa %4d: %.3f s (%d iterations, "
+                        "converged %s), planted support %d/%d" % (form, N, n, kappa, el, k, conv,
+                                                                  found, kappa))
+                    rec.update({form + "_solve_s": el, form + "_iterations": k,
+                                form + "_converged": conv, form + "_planted_found": found})
+                    P.close()
+                rec["woodbury_speedup"] = rec["default_solve_s"] / rec["woodbury_solve_s"]
+                rows_out.append(rec)
+                del parts
+        out["feature_scaling"] = rows_out
+
+    if "samples" in sweeps:
+        n, kappa, m_max = 4000, 800, 300000
+        supp, val = datagen.linear_model(41, n, kappa)
+        x_true = torch.zeros(n, dtype=torch.float64, device="cuda")
+        x_true[torch.as_tensor(supp, dtype=torch.long, device="cuda")] = torch.as_tensor(
+            val, dtype=torch.float64, device="cuda")
+        src = []
+        t = time.perf_counter()
+        for i in range(8):
+            A32 = np.empty((m_max, n), dtype=np.float32)
+            datagen.lib().bcd_gaussian_block(41, datagen.S_A + i, m_max, n, 0, 0, datagen._p(A32),
+                                             None, n)
+            src.append(torch.from_numpy(A32).cuda())
+            del A32
+        log("samples: 8 x %d x %d drawn and resident (%.1f s)" % (m_max, n, time.perf_counter() - t))
+        rows_out = []
+        for N in (2, 4, 8):
+            for mp in (25000, 50000, 100000, 200000, 300000):
+                P = bca.Problem("squared", n, [mp] * N, 1, kappa, **kw)
+                for i in range(N):
+                    A = src[i][:mp].double()
+                    A /= A.norm(dim=0, keepdim=True)
+                    gen = torch.Generator(device="cuda").manual_seed(41000 + 8 * mp + i)
+                    b = A @ x_true + noise * torch.randn(mp, dtype=torch.float64, device="cuda",
+                                                          generator=gen)
+                    P.set_data(i, A.float(), b)
+                    del A, b
+                el, k, conv, found = solve_case(P, supp)
+                total += el
+                log("samples: N %d m_i %6d: %.3f s (%d iterations, converged %s), planted "
+                    "support %d/%d" % (N, mp, el, k, conv, found, kappa))
+                rows_out.append({"N": N, "m_per": mp, "n": n, "kappa": kappa, "solve_s": el,
+                                 "iterations": k, "converged": conv, "planted_found": found})
+                P.close()
+        del src
+        out["sample_scaling"] = rows_out
+    out["value"] = total
+    out["steps"] = 0
+    out["warmup"] = 0
+    out["ms_per_step"] = None
+    print(json.dumps(out), flush=True)
+
+
+def woodbury_bench(args):
+    """Sample-space (Woodbury) x-step beside the default one on a wide problem:
+    sparse linear regression on 8 partitions of 800 x 10,000 FP32 (the largest
+    shape of the paper's feature-scaling runs: iid N(0,1), unit-norm columns per
+    partition, planted model of kappa = 2,000 nonzeros of values +-U(1,2), noise
+    0.05), one feature block, K_in = 5.  Timed over `steps` outer iterations with
+    the kernel split; the sample-space symmetric products read the distinct
+    entries of every S_ij^-1 (800 x 800) once per inner iteration, against the
+    default form's A pass and 10,000 x 10,000 inverse per partition."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    N, m, n, kappa = 8, 800, 10000, 2000
+    supp, val = datagen.linear_model(31, n, kappa)
+    kw = dict(gamma=10.0, rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5, dtype="f32",
+              max_iters=args.warmup + args.steps)
+    parts = [datagen.linear_partition(31, i, m, n, supp, val, 0.05, "f32", True) for i in range(N)]
+    res, probs = {}, {}
+    for name in ("default", "woodbury"):
+        P = bca.Problem("squared", n, [m] * N, 1, kappa, woodbury=name == "woodbury", **kw)
+        for i, (A, b) in enumerate(parts):
+            P.set_data(i, A, b)
+        P.set_timing(True)
+        t = time.perf_counter()
+        P.finalize()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        _, gram_ms = P.timing(bca.KC_GRAM)
+        _, fac_ms = P.timing(bca.KC_FACTOR)
+        P.set_timing(False)
+        P.step(args.warmup)
+        torch.cuda.synchronize()
+        P.set_timing(True)
+        t0 = time.perf_counter()
+        P.step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n_so, so_ms = P.timing(bca.KC_SOLVE)
+        n_st, st_ms = P.timing(bca.KC_STREAM)
+        n_gl, gl_ms = P.timing(bca.KC_GLOBAL)
+        P.set_timing(False)
+        r = {"iter_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
+             "kernels_ms_per_step": {"stream": st_ms / args.steps, "solve": so_ms / args.steps,
+                                     "global": gl_ms / args.steps},
+             "setup": {"seconds": setup_s, "gram_ms": gram_ms, "factor_ms": fac_ms}}
+        if name == "woodbury":
+            # per inner iteration: the stored tiles of every S_ij^-1 (one block per partition)
+            T = (m + 63) // 64
+            sym_bytes = N * T * (T + 1) // 2 * 64 * 64 * 8
+            inner_ms = (so_ms - 0.0) / max(n_so, 1)
+            ach = sym_bytes / (inner_ms / 1e3) / 1e9
+            # two passes over A per outer iteration (A w, then A^T r)
+            a_bytes = N * m * n * 4
+            pass_ms = st_ms / max(n_st, 1)
+            r["sample_space_symv"] = {"bytes_per_launch": sym_bytes, "avg_launch_ms": inner_ms,
+                                      "achieved_gbps": ach}
+            r["a_pass"] = {"bytes_per_launch": a_bytes, "avg_launch_ms": pass_ms,
+                           "achieved_gbps": a_bytes / (pass_ms / 1e3) / 1e9}
+        log("%s: %.1f iter/s, setup %.3f s, kernels ms/iter %s" % (name, args.steps / el, setup_s,
+                                                                 r["kernels_ms_per_step"]))
+        res[name] = r
+        probs[name] = P
+    d, wb = probs["default"], probs["woodbury"]
+    zd, zw = d.get_vector(bca.VEC_Z), wb.get_vector(bca.VEC_Z)
+    agree = {"z_rel_diff": float(np.linalg.norm(zd - zw) / max(np.linalg.norm(zw), 1e-300)),
+             "same_support": bool(np.array_equal(d.support(), wb.support()))}
+    for P in probs.values():
+        P.close()
+    out = {"metric": "ADMM iter/s (sample-space x-step beside the default one)",
+           "value": res["woodbury"]["iter_per_s"], "unit": "iter/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["woodbury"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "slinr_8x800x10000_f32_woodbury", "N": N, "m_per_partition": m,
+                      "n": n, "M": 1, "kappa": kappa, "inner_iters": 5},
+           "woodbury": res["woodbury"], "default": res["default"], "agreement": agree}
+    print(json.dumps(out), flush=True)
+
+
 def exact_bench(args):
     """Exact x-update (squared loss) beside Algorithm 2 on the same data: sparse
     linear regression, 16 partitions of 100,000 x 10,000 FP32 (the precision
@@ -563,17 +792,20 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve", "precision",
-                                                         "paper-shapes", "exact"],
+                                                         "paper-shapes", "paper-sweeps", "exact", "woodbury"],
                     help="plain: one problem (default); batched: many uneven problems in one "
                          "persistent launch; serve: continuous batching on a Poisson trace; precision: "
                          "BF16 beside FP32 at 16 x 100,000 x 10,000; paper-shapes: the sparse least-squares "
-                         "shapes of the paper's Table 1, end to end; exact: the exact squared-loss x-update beside "
-                         "Algorithm 2 at 16 x 100,000 x 10,000 FP32")
+                         "shapes of the paper's Table 1, end to end; paper-sweeps: the paper's rho_b convergence study and its feature and sample scaling runs; exact: the exact squared-loss x-update beside "
+                         "Algorithm 2 at 16 x 100,000 x 10,000 FP32; woodbury: the sample-space x-step beside the "
+                         "default one at 8 x 800 x 10,000 FP32")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
     ap.add_argument("--m-per", type=int, default=0,
                     help="precision: rows per partition (default 100,000; smaller values shrink n too)")
+    ap.add_argument("--sweep", default="all", choices=["all", "rho_b", "features", "samples"],
+                    help="paper-sweeps: which of the paper's Sec. 4 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: all partitions live in one GPU's memory and "
@@ -605,6 +837,10 @@ def main():
         return paper_shapes_bench(args)
     if args.mode == "exact":
         return exact_bench(args)
+    if args.mode == "paper-sweeps":
+        return paper_sweeps_bench(args)
+    if args.mode == "woodbury":
+        return woodbury_bench(args)
 
     t = time.perf_counter()
     w = workload(args.workload)

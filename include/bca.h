@@ -101,6 +101,23 @@ typedef struct {
  * Not available in the batched and serving forms. */
 enum { BCA_FLAG_EXACT_X = 1 };
 
+/* WOODBURY, one-class losses (squared, logistic, hinge): the same iteration
+ * (Algorithm 2's x_ij-step, inner_iters per outer iteration) computed in the
+ * sample space, for blocks with fewer rows than columns (m_i < n_j).  By the
+ * matrix inversion lemma the x_ij-step's new block prediction is
+ * p+ = d - shift S_ij^-1 d + rho_c S_ij^-1 A_ij (z_j - u_ij) with
+ * S_ij = rho_l A_ij A_ij^T + shift I (m_i x m_i, shift = 1/(N gamma) + rho_c)
+ * and d = p_ij + e, so the inner iterations read only the cached S_ij^-1
+ * (m_i^2 / 2 FP64 entries per block, formed once at finalize from FP64 sums)
+ * and A is read twice per outer iteration: once for A_ij (z_j - u_ij) and
+ * p_ij = A_ij x_ij (d is re-derived from the state at every outer iteration),
+ * once for x_ij = (rho_l / shift) A_ij^T (d - p+) + (rho_c / shift)(z_j - u_ij).  Results
+ * equal those of the default form up to rounding.  Device memory: N M
+ * ceil(mw/64) (ceil(mw/64) + 1) / 2 tiles of 32 KB, mw = max_i m_i, instead of
+ * the n_j x n_j inverses.  bca_get_inverse then fails with BCA_E_STATE; not
+ * available with EXACT_X, softmax, or in the batched and serving forms. */
+enum { BCA_FLAG_WOODBURY = 2 };
+
 /* Create a problem: validates the parameters and allocates device memory for
  * the data and the ADMM state.  hip_stream is a hipStream_t (may be NULL).
  * Errors: BCA_E_INVALID (parameter out of range), BCA_E_OOM, BCA_E_DEVICE. */

@@ -20,6 +20,7 @@ ERRORS = {-1: "BCA_E_INVALID", -2: "BCA_E_OOM", -3: "BCA_E_STATE", -4: "BCA_E_NO
           -5: "BCA_E_DEVICE", -6: "BCA_E_BUDGET", -7: "BCA_E_NOTFOUND", -8: "BCA_E_CANCELLED"}
 LOSS = {"squared": 0, "logistic": 1, "softmax": 2, "hinge": 3}
 FLAG_EXACT_X = 1
+FLAG_WOODBURY = 2
 DTYPE = {"f64": 0, "f32": 1, "bf16": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 VEC_X, VEC_U, VEC_Z, VEC_S, VEC_OMEGA, VEC_NU, VEC_TV = range(7)
@@ -139,7 +140,8 @@ class Problem:
                  gamma: float = 10.0, rho_c: float = 1.0, rho_b: float = 0.5,
                  rho_l: float = 1.0, inner_iters: int = 5, max_iters: int = 100,
                  dtype: str = "f32", n_classes: int = 1, tol=(1e-6, 1e-6, 1e-6),
-                 check_every: int = 10, stream=None, exact_x: bool = False):
+                 check_every: int = 10, stream=None, exact_x: bool = False,
+                 woodbury: bool = False):
         self.loss, self.n, self.dtype = loss, n, dtype
         self.rows = [int(r) for r in rows]
         # the exact x-update factors all n features as one block
@@ -150,7 +152,8 @@ class Problem:
                    n_blocks=n_blocks, kappa=kappa, rows=self._rows, gamma=gamma, rho_c=rho_c,
                    rho_b=rho_b, rho_l=rho_l, inner_iters=inner_iters, max_iters=max_iters,
                    tol_p=tol[0], tol_d=tol[1], tol_b=tol[2], a_dtype=DTYPE[dtype],
-                   check_every=check_every, flags=FLAG_EXACT_X if exact_x else 0)
+                   check_every=check_every,
+                   flags=(FLAG_EXACT_X if exact_x else 0) | (FLAG_WOODBURY if woodbury else 0))
         self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
         h = ctypes.c_void_p()
         _check(_lib.bca_create(ctypes.byref(p), self._stream, ctypes.byref(h)))

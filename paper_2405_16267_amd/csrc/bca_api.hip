@@ -13,6 +13,9 @@
 //                             (sum_ij T_ij (T_ij + 1) / 2 tiles, T_ij = ceil(n_j / 64))
 //   ypart                     N M x tmax x tmax x 64 doubles: slots of the symmetric product
 //   atb                       exact x-update only: N x n doubles, 2 A_i^T b_i
+//   sample-space x-step (BCA_FLAG_WOODBURY) instead of the n_j x n_j inverses:
+//   kinv                      S_ij^-1 as tiles, mw = max_i m_i rows per block (padded)
+//   wt, wh, wd, wr            N x M x mw doubles each (A w, S^-1 A w, d, d - p+)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -94,6 +97,15 @@ struct bca_problem_s {
   bool finalized = false;
   bool exact = false;        // BCA_FLAG_EXACT_X: exact x-update, one block
   double* atb = nullptr;
+  bool wood = false;         // BCA_FLAG_WOODBURY: sample-space x-step
+  int mw = 0, Gw = 1;        // padded rows per block; row chunks of the A^T r pass
+  int64_t wkmat_total = 0;
+  std::vector<int64_t> wfac_off, wkmat_off;
+  std::vector<int32_t> wcol_off;
+  double *wt = nullptr, *wh = nullptr, *wd = nullptr, *wr = nullptr;
+  int64_t* d_wfac_off = nullptr;
+  int64_t* d_wkmat_off = nullptr;
+  int32_t* d_wcol_off = nullptr;
   bool need_prime = false;
   int iter = 0;
   bool timing = false;
@@ -287,12 +299,63 @@ GlobalArgs global_args(bca_problem P) {
   return g;
 }
 
+WoodArgs wood_args(bca_problem P, int mode) {
+  WoodArgs a{};
+  a.A = P->A;
+  a.ld = P->ld;
+  a.row_off = P->d_row_off;
+  a.col_off = P->d_col_off;
+  a.b = P->b;
+  a.omega = P->omega;
+  a.nu = P->nu;
+  a.x = P->x;
+  a.u = P->u;
+  a.z = P->z;
+  a.wt = P->wt;
+  a.wh = P->wh;
+  a.wd = P->wd;
+  a.wr = P->wr;
+  a.ypart = P->ypart;
+  a.gpart = P->gpart;
+  a.kmat_off = P->d_wkmat_off;
+  a.N = P->N;
+  a.M = P->M;
+  a.n = P->n;
+  a.mw = P->mw;
+  a.Gp = P->Gp;
+  a.Gw = P->Gw;
+  a.loss = P->p.loss;
+  a.mode = mode;
+  a.rho_l = P->p.rho_l;
+  a.rho_c = P->p.rho_c;
+  a.shift = P->shift;
+  a.inv_M = 1.0 / P->M;
+  return a;
+}
+
+// The symmetric product with the cached S_ij^-1 of every block, rhs in the
+// sample-space layout (N x M x mw).
+SolveArgs wood_symv_args(bca_problem P, const double* rhs) {
+  SolveArgs a = solve_args(P);
+  a.rhs = const_cast<double*>(rhs);
+  a.fac_off = P->d_wfac_off;
+  a.col_off = P->d_wcol_off;
+  a.n = P->M * P->mw;
+  a.C = 1;
+  a.nj_max = P->mw;
+  return a;
+}
+
 int launch_ok(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(BCA_E_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
   return BCA_OK;
 }
 
 int prime(bca_problem P) {
+  if (P->wood) {  // every outer iteration re-derives d from the state
+    P->need_prime = false;
+    return BCA_OK;
+  }
   if (P->exact) {  // no inner loop: nothing to re-derive from the state
     P->need_prime = false;
     return BCA_OK;
@@ -304,7 +367,40 @@ int prime(bca_problem P) {
   return BCA_OK;
 }
 
+int one_outer_wood(bca_problem P) {
+  const WoodArgs wa = wood_args(P, 0);
+  {
+    Timer t(P, BCA_KC_STREAM);
+    TRY(launch_ok(launch_wgemv_n(wa, P->dtype, P->stream), "wgemv_n"));
+  }
+  {
+    Timer t(P, BCA_KC_SOLVE);
+    TRY(launch_ok(launch_symv(wood_symv_args(P, P->wt), P->stream), "symv(S, A w)"));
+    TRY(launch_ok(launch_wgather(wa, P->stream), "wgather"));
+    WoodArgs wp = wa;
+    wp.mode = 1;
+    TRY(launch_ok(launch_wupdate(wp, P->stream), "wupdate(d from the state)"));
+  }
+  const SolveArgs sd = wood_symv_args(P, P->wd);
+  for (int k = 0; k < P->p.inner_iters; ++k) {
+    Timer t(P, BCA_KC_SOLVE);
+    TRY(launch_ok(launch_symv(sd, P->stream), "symv(S, d)"));
+    TRY(launch_ok(launch_wupdate(wa, P->stream), "wupdate"));
+  }
+  {
+    Timer t(P, BCA_KC_STREAM);
+    TRY(launch_ok(launch_wgemv_t(wa, P->dtype, P->stream), "wgemv_t"));
+  }
+  {
+    Timer t(P, BCA_KC_GLOBAL);
+    TRY(launch_ok(launch_global(global_args(P), P->stream), "global"));
+  }
+  P->iter += 1;
+  return BCA_OK;
+}
+
 int one_outer(bca_problem P) {
+  if (P->wood) return one_outer_wood(P);
   const SolveArgs sa = solve_args(P);
   if (P->exact) {
     {
@@ -370,7 +466,12 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     return fail(BCA_E_INVALID, "gamma, rho_c, rho_b, rho_l must be > 0");
   if (p.inner_iters < 1 || p.max_iters < 1) return fail(BCA_E_INVALID, "inner_iters and max_iters must be >= 1");
   if (p.a_dtype < 0 || p.a_dtype > 2) return fail(BCA_E_INVALID, "unknown a_dtype %d", p.a_dtype);
-  if (p.flags & ~(uint32_t)BCA_FLAG_EXACT_X) return fail(BCA_E_INVALID, "unknown flags 0x%x", p.flags);
+  if (p.flags & ~(uint32_t)(BCA_FLAG_EXACT_X | BCA_FLAG_WOODBURY))
+    return fail(BCA_E_INVALID, "unknown flags 0x%x", p.flags);
+  if ((p.flags & BCA_FLAG_EXACT_X) && (p.flags & BCA_FLAG_WOODBURY))
+    return fail(BCA_E_INVALID, "BCA_FLAG_EXACT_X and BCA_FLAG_WOODBURY exclude each other");
+  if ((p.flags & BCA_FLAG_WOODBURY) && p.loss == BCA_LOSS_SOFTMAX)
+    return fail(BCA_E_INVALID, "the sample-space x-step handles one-class losses only");
   if ((p.flags & BCA_FLAG_EXACT_X) && p.loss != BCA_LOSS_SQUARED)
     return fail(BCA_E_INVALID, "the exact x-update needs the squared loss");
   for (int i = 0; i < p.n_partitions; ++i)
@@ -411,6 +512,22 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     }
   P->fac_total = fo;
   P->kmat_total = ko;
+  P->wood = (p.flags & BCA_FLAG_WOODBURY) != 0;
+  if (P->wood) {
+    // one mw x mw matrix S_ij per block, mw = the tallest partition
+    for (auto r : P->rows) P->mw = (int)std::max<int64_t>(P->mw, r);
+    P->wcol_off.resize(P->M + 1);
+    for (int j = 0; j <= P->M; ++j) P->wcol_off[j] = j * P->mw;
+    const int64_t nb = (int64_t)P->N * P->M;
+    P->wfac_off.resize(nb);
+    P->wkmat_off.resize(nb);
+    for (int64_t q = 0; q < nb; ++q) {
+      P->wfac_off[q] = q * ptile_count(P->mw) * PT_ELEMS;
+      P->wkmat_off[q] = q * (int64_t)P->mw * P->mw;
+    }
+    P->fac_total = nb * ptile_count(P->mw) * PT_ELEMS;   // kinv holds the S_ij^-1
+    P->wkmat_total = nb * (int64_t)P->mw * P->mw;
+  }
   P->shift = 1.0 / (P->N * p.gamma) + p.rho_c;
   const int VEC = (P->dtype == BCA_F64) ? 2 : (P->dtype == BCA_F32 ? 4 : 8);
   P->nvec = (P->n + VEC - 1) / VEC;
@@ -457,7 +574,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->u, (size_t)P->N * P->n * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->rhs, (size_t)P->N * P->n * C));
   if (rc == BCA_OK) {
-    const int64_t tm = (P->nj_max + PT - 1) / PT;
+    const int64_t tm = ((P->wood ? P->mw : P->nj_max) + PT - 1) / PT;
     chk(dalloc(P, &P->ypart, (size_t)(P->N * P->M) * tm * tm * PT * C));
   }
   if (rc == BCA_OK) {
@@ -479,6 +596,21 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->gpart, (size_t)P->N * P->Gp * P->ld * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->kinv, (size_t)P->fac_total));
   if (rc == BCA_OK && P->exact) chk(dalloc(P, &P->atb, (size_t)P->N * P->n));
+  if (P->wood) {
+    const size_t nw = (size_t)P->N * P->M * P->mw;
+    if (rc == BCA_OK) chk(dalloc(P, &P->wt, nw));
+    if (rc == BCA_OK) chk(dalloc(P, &P->wh, nw));
+    if (rc == BCA_OK) chk(dalloc(P, &P->wd, nw));
+    if (rc == BCA_OK) chk(dalloc(P, &P->wr, nw));
+    if (rc == BCA_OK) chk(dalloc(P, &P->d_wfac_off, P->wfac_off.size()));
+    if (rc == BCA_OK) chk(dalloc(P, &P->d_wkmat_off, P->wkmat_off.size()));
+    if (rc == BCA_OK) chk(dalloc(P, &P->d_wcol_off, P->M + 1));
+    // A^T r row chunks: enough workgroups to fill the GPU, at least 8 rows each
+    const int64_t cgroups = (P->n + 255) / 256;
+    int64_t gw = (2048 + cgroups * P->N - 1) / (cgroups * P->N);
+    gw = std::min<int64_t>(gw, std::min<int64_t>(P->Gp, (P->mw + 7) / 8));
+    P->Gw = (int)std::max<int64_t>(1, gw);
+  }
   if (rc == BCA_OK) chk(dalloc(P, &P->objpart, (size_t)P->N * P->Gp));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_row_off, P->N + 1));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_col_off, P->M + 1));
@@ -499,6 +631,11 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (e == hipSuccess) e = cp(P->d_col_off, P->col_off.data(), (P->M + 1) * sizeof(int32_t));
   if (e == hipSuccess) e = cp(P->d_fac_off, P->fac_off.data(), P->fac_off.size() * sizeof(int64_t));
   if (e == hipSuccess) e = cp(P->d_kmat_off, P->kmat_off.data(), P->kmat_off.size() * sizeof(int64_t));
+  if (e == hipSuccess && P->wood) {
+    e = cp(P->d_wfac_off, P->wfac_off.data(), P->wfac_off.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = cp(P->d_wkmat_off, P->wkmat_off.data(), P->wkmat_off.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = cp(P->d_wcol_off, P->wcol_off.data(), P->wcol_off.size() * sizeof(int32_t));
+  }
   if (e == hipSuccess) e = hipMemsetAsync(P->A, 0, (size_t)P->m_total * P->ld * es, s);
   if (e == hipSuccess) e = hipMemsetAsync(P->status, 0, 4 * sizeof(int), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -560,14 +697,15 @@ int bca_finalize(bca_problem P) {
   for (int i = 0; i < P->N; ++i)
     if (!P->loaded[i]) return fail(BCA_E_STATE, "partition %d has no data", i);
   double *kbuf = nullptr, *wbuf = nullptr;
-  TRY(dalloc(P, &kbuf, (size_t)P->kmat_total));
-  int rc = dalloc(P, &wbuf, (size_t)P->kmat_total);
+  const int64_t kmat_total = P->wood ? P->wkmat_total : P->kmat_total;
+  TRY(dalloc(P, &kbuf, (size_t)kmat_total));
+  int rc = dalloc(P, &wbuf, (size_t)kmat_total);
   if (rc != BCA_OK) {
     dfree(P, kbuf);
     return rc;
   }
   hipStream_t s = P->stream;
-  hipError_t e = hipMemsetAsync(wbuf, 0, (size_t)P->kmat_total * sizeof(double), s);
+  hipError_t e = hipMemsetAsync(wbuf, 0, (size_t)kmat_total * sizeof(double), s);
   if (e == hipSuccess) e = hipMemsetAsync(P->status, 0, sizeof(int), s);
   GramArgs g{};
   g.A = P->A;
@@ -593,9 +731,21 @@ int bca_finalize(bca_problem P) {
   f.N = P->N;
   f.M = P->M;
   f.nj_max = P->nj_max;
+  if (P->wood) {  // factor the S_ij (mw x mw) instead of the K_ij
+    f.kmat_off = P->d_wkmat_off;
+    f.col_off = P->d_wcol_off;
+    f.fac_off = P->d_wfac_off;
+    f.nj_max = P->mw;
+  }
   if (e == hipSuccess) {
     Timer t(P, BCA_KC_GRAM);
-    e = launch_gram(g, P->dtype, s);
+    if (P->wood) {
+      WoodArgs wa = wood_args(P, 0);
+      wa.kbuf = kbuf;
+      e = launch_rowgram(wa, P->dtype, s);
+    } else {
+      e = launch_gram(g, P->dtype, s);
+    }
   }
   if (e == hipSuccess) {
     Timer t(P, BCA_KC_FACTOR);
@@ -618,6 +768,13 @@ int bca_finalize(bca_problem P) {
   if (e == hipSuccess)
     e = hipMemsetAsync(P->gpart, 0, (size_t)P->N * P->Gp * P->ld * P->C * sizeof(double), s);
   if (e == hipSuccess) e = hipMemsetAsync(P->support, 0, (size_t)P->kappa * sizeof(int32_t), s);
+  if (e == hipSuccess && P->wood) {  // zero state: d = p + e = 0
+    const size_t nw = (size_t)P->N * P->M * P->mw * sizeof(double);
+    e = hipMemsetAsync(P->wt, 0, nw, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P->wh, 0, nw, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P->wd, 0, nw, s);
+    if (e == hipSuccess) e = hipMemsetAsync(P->wr, 0, nw, s);
+  }
   if (e == hipSuccess && P->exact) {
     // 2 A_i^T b_i, streamed once: the re-derivation pass with omega-bar = b, nu = 0
     // and x = 0 accumulates sum_k b_k a_k, and the reduction scales it by 2
@@ -642,7 +799,7 @@ int bca_finalize(bca_problem P) {
   dfree(P, kbuf);
   dfree(P, wbuf);
   if (e != hipSuccess) return fail(BCA_E_DEVICE, "finalize: %s", hipGetErrorString(e));
-  if (st) return fail(BCA_E_NONFINITE, "finalize: a block matrix K_ij is not positive definite");
+  if (st) return fail(BCA_E_NONFINITE, "finalize: a block matrix K_ij (S_ij) is not positive definite");
   P->finalized = true;
   P->need_prime = false;
   P->need_bprime = true;
@@ -904,6 +1061,7 @@ int bca_get_inverse(bca_problem P, int32_t part, int32_t block, double* Kinv) {
   if (!P || !Kinv) return fail(BCA_E_INVALID, "null argument");
   if (!P->finalized) return fail(BCA_E_STATE, "no inverse before finalize");
   if (part < 0 || part >= P->N || block < 0 || block >= P->M) return fail(BCA_E_INVALID, "index out of range");
+  if (P->wood) return fail(BCA_E_STATE, "the sample-space x-step forms no n_j x n_j inverse");
   const int nj = P->col_off[block + 1] - P->col_off[block];
   const int T = (nj + PT - 1) / PT;
   std::vector<double> tiles((size_t)ptile_count(nj) * PT_ELEMS);
@@ -988,6 +1146,7 @@ int batch_check(bca_problem P) {
   if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
   if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
   if (P->exact) return fail(BCA_E_INVALID, "the batched form runs Algorithm 2's inner loop (no exact x-update)");
+  if (P->wood) return fail(BCA_E_INVALID, "the batched form runs the n_j x n_j x-step (no sample-space x-step)");
   if (P->dtype == BCA_BF16) return fail(BCA_E_INVALID, "the batched form streams FP32 or FP64 data");
   if (P->nj_max > 1024 || P->nvec > batch_max_nvec())
     return fail(BCA_E_INVALID, "batched problems need n_j <= 1024 and n <= 64*8 vectors per row");
@@ -1000,6 +1159,7 @@ int batch_check_basic(bca_problem P) {
   if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
   if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
   if (P->exact) return fail(BCA_E_INVALID, "the batched form runs Algorithm 2's inner loop (no exact x-update)");
+  if (P->wood) return fail(BCA_E_INVALID, "the batched form runs the n_j x n_j x-step (no sample-space x-step)");
   if (P->dtype == BCA_BF16) return fail(BCA_E_INVALID, "the batched form streams FP32 or FP64 data");
   if (P->nj_max > 1024 || P->nvec > batch_max_nvec())
     return fail(BCA_E_INVALID, "batched problems need n_j <= 1024 and n <= 64*8 vectors per row");

@@ -233,6 +233,8 @@ struct SolveArgs {
   double rho_l, rho_c, shift;
 };
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+// Only the symmetric product y = P_ij rhs_ij, into the slots at ypart.
+hipError_t launch_symv(const SolveArgs& a, hipStream_t s);
 // rhs = rho_l sum_w gpart[w] + rho_c (z - u) - shift x only.
 hipError_t launch_reduce_rhs(const SolveArgs& a, hipStream_t s);
 // Exact x-update (squared loss, one block per partition): x = P (atb + rho_c (z - u)).
@@ -258,6 +260,49 @@ hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* id
 // T_kappa of z (rows by Euclidean norm when C > 1); work holds n doubles.
 hipError_t launch_support(const double* z, int n, int C, int kappa, int32_t* idx, double* work,
                           hipStream_t s);
+
+// ------------------------------------------------------------------ sample-space x_ij-step
+// Woodbury form of the x_ij-step for blocks with fewer rows than columns
+// (m_i < n_j): with S_ij = shift I + rho_l A_ij A_ij^T (m_i x m_i), the update
+// x+ = K_ij^-1 (rho_l A_ij^T d_ij + rho_c w_j), w_j = z_j - u_ij, maps the block
+// prediction p_ij = A_ij x_ij to
+//     p+ = d - shift S^-1 d + rho_c S^-1 A_ij w_j,
+// and after the last inner iteration x+ = (rho_l / shift) A_ij^T (d - p+) +
+// (rho_c / shift) w_j.  Sample-space vectors are N x M x mw doubles (block (i, j)
+// at (i M + j) mw, rows past m_i zero), mw = max_i m_i.
+struct WoodArgs {
+  const void* A;
+  int64_t ld;
+  const int64_t* row_off;  // N + 1
+  const int32_t* col_off;  // M + 1 (feature blocks)
+  const double* b;
+  double* omega;
+  double* nu;
+  double* x;               // N x n
+  const double* u;         // N x n
+  const double* z;         // n
+  double* wt;              // A_ij w_j
+  double* wh;              // S^-1 A_ij w_j
+  double* wd;              // d_ij = p_ij + e
+  double* wr;              // A_ij x_ij, then d_ij - p+_ij of the last inner iteration
+  const double* ypart;     // slots of the sample-space symmetric products
+  double* gpart;           // N x Gp x ld partial sums of A^T r
+  double* kbuf;            // setup: dense S_ij, mw x mw each, at kmat_off
+  const int64_t* kmat_off; // N*M
+  int N, M, n, mw, Gp, Gw, loss, mode;
+  double rho_l, rho_c, shift, inv_M;
+};
+// S_ij = rho_l A_ij A_ij^T + shift I (lower part, FP64 sums), padded rows: shift I.
+hipError_t launch_rowgram(const WoodArgs& a, int dtype, hipStream_t s);
+// wt = A_ij (z_j - u_ij) and wr = A_ij x_ij, one pass over A.
+hipError_t launch_wgemv_n(const WoodArgs& a, int dtype, hipStream_t s);
+// x = (rho_l / shift) A_ij^T wr + (rho_c / shift)(z - u), one pass over A.
+hipError_t launch_wgemv_t(const WoodArgs& a, int dtype, hipStream_t s);
+// wh = the gathered symmetric product (after symv of wt).
+hipError_t launch_wgather(const WoodArgs& a, hipStream_t s);
+// mode 0: one inner iteration from the gathered S^-1 d; mode 1: d = wr + e, e
+// from the stored omega-bar and nu.
+hipError_t launch_wupdate(const WoodArgs& a, hipStream_t s);
 
 // ------------------------------------------------------------------ batched form
 // Device-side descriptor of one problem of a batch (all pointers are that

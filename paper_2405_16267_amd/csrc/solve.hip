@@ -91,6 +91,14 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_symv(const SolveArgs& a, hipStream_t s) {
+  if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
+  const int64_t tiles = ptile_count(a.nj_max);
+  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
+  hipLaunchKernelGGL(symv_kernel, g2, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_rhs(const SolveArgs& a, hipStream_t s) {
   if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
   dim3 g1((unsigned)(((int64_t)a.n * a.C + 255) / 256), a.N);

@@ -22,8 +22,8 @@
 //   rowgram_kernel  S_ij = rho_l A_ij A_ij^T + shift I, 64 x 64 lower tiles,
 //                   FP64 sums of exact products (the form does not correct
 //                   rounding in S_ij later, unlike the incremental x-step)
-//   wgemv_n_kernel  A_ij w_j and A_ij x_ij per row and block, one wavefront per
-//                   2 rows
+//   wgemv_n_kernel  A_ij w_j and A_ij x_ij per row and block, one workgroup per
+//                   8 rows
 //   wgemv_t_kernel  partial sums of A_ij^T r over row chunks, one thread per
 //                   column; wxred_kernel adds them in a fixed order
 //   wgather_kernel  h = S^-1 (A w) from the symmetric product's slots
@@ -94,49 +94,75 @@ __global__ __launch_bounds__(256) void rowgram_kernel(WoodArgs a) {
     }
 }
 
-// wt = A_ij (z_j - u_ij) and wr = A_ij x_ij in one pass; two rows per wavefront,
-// four wavefronts per workgroup
+// wt = A_ij (z_j - u_ij) and wr = A_ij x_ij in one pass.  A workgroup takes WR
+// rows; its 256 threads stride over the columns, so each element of z, u and x
+// is fetched once for all WR rows (with fewer rows per fetch the kernel is bound
+// by those cached FP64 reads, not by A).  Row sums: DPP inside each wavefront,
+// then the four wavefronts in a fixed order.
+constexpr int WR = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void wgemv_n_kernel(WoodArgs a) {
+  __shared__ double red[4][2 * WR];
   const int part = blockIdx.y;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r = (blockIdx.x * 4 + wv) * 2;
-  if (r >= a.mw) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rb = blockIdx.x * WR;
   const int64_t r0 = a.row_off[part];
   const int64_t m = a.row_off[part + 1] - r0;
-  const T* A0 = reinterpret_cast<const T*>(a.A) + (r0 + r) * a.ld;
-  const bool h0 = r < m, h1 = r + 1 < m;
+  const int nr = (int)max((int64_t)0, min((int64_t)WR, m - rb));   // tile rows with data
+  const T* A0 = reinterpret_cast<const T*>(a.A) + (r0 + rb) * a.ld;
   const double* xp = a.x + (int64_t)part * a.n;
   const double* up = a.u + (int64_t)part * a.n;
   for (int j = 0; j < a.M; ++j) {
     const int c0 = a.col_off[j], c1 = a.col_off[j + 1];
-    double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0;
-    for (int k = c0 + lane; k < c1; k += 64) {
-      const double v = a.z[k] - up[k], xv = xp[k];
-      if (h0) {
-        const double e0 = elem(A0 + k);
-        s0 += e0 * v;
-        q0 += e0 * xv;
+    double sw[WR], sx[WR];
+#pragma unroll
+    for (int q = 0; q < WR; ++q) sw[q] = sx[q] = 0.0;
+    // branch-free loads: rows past the partition's end read its last row and
+    // count zero times
+    if (nr > 0) {
+      const T* rp[WR];
+      double keep[WR];
+#pragma unroll
+      for (int q = 0; q < WR; ++q) {
+        rp[q] = A0 + (int64_t)min(q, nr - 1) * a.ld;
+        keep[q] = q < nr ? 1.0 : 0.0;
       }
-      if (h1) {
-        const double e1 = elem(A0 + a.ld + k);
-        s1 += e1 * v;
-        q1 += e1 * xv;
+#pragma unroll 2
+      for (int k = c0 + tid; k < c1; k += 256) {
+        const double v = a.z[k] - up[k], xv = xp[k];
+        double e[WR];
+#pragma unroll
+        for (int q = 0; q < WR; ++q) e[q] = elem(rp[q] + k);
+#pragma unroll
+        for (int q = 0; q < WR; ++q) {
+          const double eq = e[q] * keep[q];
+          sw[q] += eq * v;
+          sx[q] += eq * xv;
+        }
       }
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    q0 = wave_sum(q0);
-    q1 = wave_sum(q1);
+#pragma unroll
+    for (int q = 0; q < WR; ++q) {
+      sw[q] = wave_sum_dpp(sw[q]);
+      sx[q] = wave_sum_dpp(sx[q]);
+    }
     if (lane == 0) {
-      const int64_t o = ((int64_t)part * a.M + j) * a.mw;
-      a.wt[o + r] = s0;
-      a.wr[o + r] = q0;
-      if (r + 1 < a.mw) {
-        a.wt[o + r + 1] = s1;
-        a.wr[o + r + 1] = q1;
+#pragma unroll
+      for (int q = 0; q < WR; ++q) {
+        red[wv][q] = sw[q];
+        red[wv][WR + q] = sx[q];
       }
     }
+    __syncthreads();
+    if (tid < 2 * WR) {
+      const int q = tid % WR;
+      const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      if (rb + q < a.mw) {
+        const int64_t o = ((int64_t)part * a.M + j) * a.mw + rb + q;
+        (tid < WR ? a.wt : a.wr)[o] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -244,7 +270,7 @@ hipError_t launch_rowgram(const WoodArgs& a, int dtype, hipStream_t s) {
 }
 
 hipError_t launch_wgemv_n(const WoodArgs& a, int dtype, hipStream_t s) {
-  dim3 g((unsigned)((a.mw + 7) / 8), a.N);
+  dim3 g((unsigned)((a.mw + WR - 1) / WR), a.N);
   if (dtype == BCA_F64)
     hipLaunchKernelGGL(wgemv_n_kernel<double>, g, dim3(256), 0, s, a);
   else if (dtype == BCA_F32)

@@ -173,3 +173,37 @@ def test_woodbury_parameter_checks():
     with pytest.raises(bca.BcaError):
         bca.batch_solve([P])
     P.close()
+
+
+def test_woodbury_edge_shapes_f64():
+    """A one-row partition beside one of exactly one 64-row tile (mw = 64), and
+    three ragged feature blocks (44, 43, 43 of n = 130): state after each outer
+    iteration against the oracle."""
+    w = datagen.linear_workload(87, N=2, m_per=[1, 64], n=130, kappa=4, k_true=4, noise=0.05,
+                                n_blocks=3, dtype="f64", max_iters=6)
+    P = make(w)
+    o = make_oracle(w)
+    for _ in range(w.max_iters):
+        P.step(1)
+        o.iterate(1, w.inner_iters)
+        _state_matches(P, o, w, 1e-10)
+    P.close()
+
+
+def test_woodbury_all_zero_data_stays_at_zero():
+    """A = 0 and b = 0: S_ij = shift I, and every iterate stays exactly zero."""
+    bca = _bca()
+    rows = [70, 33]
+    P = bca.Problem("squared", 90, rows, 2, 5, dtype="f32", max_iters=5, woodbury=True)
+    for i, m in enumerate(rows):
+        P.set_data(i, np.zeros((m, 90), dtype=np.float32), np.zeros(m))
+    P.finalize()
+    P.step(5)
+    assert not np.any(P.get_vector(bca.VEC_Z))
+    for i in range(len(rows)):
+        assert not np.any(P.get_vector(bca.VEC_X, i))
+        assert not np.any(P.get_vector(bca.VEC_NU, i))
+    pr, dr, br, it = P.residuals()
+    assert (pr, dr, br, it) == (0.0, 0.0, 0.0, 5)
+    assert np.array_equal(P.support(), np.arange(5))   # ties go to the lowest indices
+    P.close()

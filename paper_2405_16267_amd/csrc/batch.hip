@@ -353,6 +353,10 @@ __device__ GlobalArgs global_args_of(const BatchInst& I) {
   g.hist_cap = I.hist_cap;
   g.rho_c = I.rho_c;
   g.rho_b = I.rho_b;
+  g.gp = nullptr;   // the whole step in this workgroup
+  g.split = 0;
+  g.G = 0;
+  g.G2 = 0;
   return g;
 }
 

@@ -88,6 +88,7 @@ struct bca_problem_s {
   double* gpart = nullptr;
   double* kinv = nullptr;
   double* objpart = nullptr;
+  double* gp = nullptr;      // partial sums of the split global step
   int64_t* d_row_off = nullptr;
   int32_t* d_col_off = nullptr;
   int64_t* d_fac_off = nullptr;
@@ -296,6 +297,10 @@ GlobalArgs global_args(bca_problem P) {
   g.hist_cap = P->p.max_iters;
   g.rho_c = P->p.rho_c;
   g.rho_b = P->p.rho_b;
+  g.gp = P->gp;
+  g.split = 1;
+  g.G = global_groups(P->n);
+  g.G2 = global_groups2(P->n, P->C);
   return g;
 }
 
@@ -612,6 +617,8 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     P->Gw = (int)std::max<int64_t>(1, gw);
   }
   if (rc == BCA_OK) chk(dalloc(P, &P->objpart, (size_t)P->N * P->Gp));
+  if (rc == BCA_OK)
+    chk(dalloc(P, &P->gp, 2 * (size_t)global_groups(P->n) + (size_t)(P->N + 1) * global_groups2(P->n, C)));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_row_off, P->N + 1));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_col_off, P->M + 1));
   if (rc == BCA_OK) chk(dalloc(P, &P->d_fac_off, (size_t)P->N * P->M));

@@ -252,7 +252,14 @@ struct GlobalArgs {
   int* status;             // nonzero on NaN/Inf
   int N, n, C, kappa, hist_cap;
   double rho_c, rho_b;
+  // split form (one problem): per-workgroup partial sums of the consensus pass
+  // (2 G) and of the u-update / residual pass ((N + 1) G2); 0 in the batched form
+  double* gp;
+  int split, G, G2;
 };
+// Workgroups of the consensus pass and of the u-update pass of the split form.
+inline int global_groups(int n) { return (n + 255) / 256; }
+inline int global_groups2(int n, int C) { return (int)(((int64_t)n * C + 255) / 256); }
 hipError_t launch_global(const GlobalArgs& a, hipStream_t s);
 
 hipError_t launch_topk(const void* z, int f64, int64_t n, int kappa, int32_t* idx, double* work,

@@ -1,5 +1,8 @@
-// Global level of Algorithm 1 plus the node-level u-update, fused into one
-// workgroup of 1024 threads (the work is O(N n) and latency-bound):
+// Global level of Algorithm 1 plus the node-level u-update.  For one problem
+// the O(N n) consensus average and u-update with residuals run over many
+// workgroups (consensus_kernel, uresid_kernel, gfinal_kernel) around one
+// workgroup of 1024 threads for the O(n), latency-bound rest (global_kernel);
+// the batched kernel runs all of it in one workgroup:
 //   wbar = (1/N) sum_i (x_i + u_i)                         consensus average
 //   (z, t) = argmin_{||z||_1 <= t} (a/2)||z - wbar||^2 + (rho_b/2)(s^T z - t + v)^2
 //   s = clip((t - v)/M_kappa, -1, 1) sign(z) on T_kappa(z)  (s-step, Sec. 3)
@@ -27,9 +30,90 @@ __global__ __launch_bounds__(GT) void global_kernel(GlobalArgs a) {
   global_step<GT>(a, shd, tks);
 }
 
+// Split form, one problem: the O(N n) passes over many workgroups.
+// consensus_kernel: one thread per row k; partial sum of d_k |wbar_k| and
+// maximum finite breakpoint per workgroup into gp[g], gp[G + g].
+__global__ __launch_bounds__(256) void consensus_kernel(GlobalArgs a) {
+  __shared__ double shd[4];
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  double s1 = 0.0, thm = 0.0;
+  bool bad = false;
+  if (k < a.n) consensus_row(a, k, &s1, &thm, &bad);
+  if (bad) atomicExch(a.status, 1);
+  s1 = block_sum<256>(s1, shd);
+  thm = block_max<256>(thm, shd);
+  if (threadIdx.x == 0) {
+    a.gp[blockIdx.x] = s1;
+    a.gp[a.G + blockIdx.x] = thm;
+  }
+}
+
+// uresid_kernel: grid (G2, N + 1).  Row i < N: u_i += x_i - z and the partial
+// sum of |x_i - z|^2 into gp[2G + i G2 + g]; row N: the partial sum of
+// |z - z_prev|^2 into gp[2G + N G2 + g].
+__global__ __launch_bounds__(256) void uresid_kernel(GlobalArgs a) {
+  __shared__ double shd[4];
+  const int i = blockIdx.y;
+  const int64_t nc = (int64_t)a.n * a.C;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (e < nc) {
+    if (i < a.N) {
+      const int64_t o = (int64_t)i * nc + e;
+      const double d = a.x[o] - a.z[e];
+      acc = d * d;
+      a.u[o] += d;
+    } else {
+      const double d = a.z[e] - a.work[nc + e];   // z_prev, saved by the consensus pass
+      acc = d * d;
+    }
+  }
+  acc = block_sum<256>(acc, shd);
+  if (threadIdx.x == 0) a.gp[2 * (int64_t)a.G + (int64_t)i * a.G2 + blockIdx.x] = acc;
+}
+
+// gfinal_kernel: one workgroup; residuals from the partial sums in a fixed order.
+__global__ __launch_bounds__(256) void gfinal_kernel(GlobalArgs a) {
+  __shared__ double shd[4];
+  const double* p = a.gp + 2 * (int64_t)a.G;
+  double pr = 0.0;
+  for (int i = 0; i < a.N; ++i) {
+    double pl = 0.0;
+    for (int g = threadIdx.x; g < a.G2; g += 256) pl += p[(int64_t)i * a.G2 + g];
+    pr += sqrt(block_sum<256>(pl, shd));
+  }
+  double dz = 0.0;
+  for (int g = threadIdx.x; g < a.G2; g += 256) dz += p[(int64_t)a.N * a.G2 + g];
+  const double dzs = block_sum<256>(dz, shd);
+  if (threadIdx.x == 0) {
+    const double dr = sqrt((double)a.N) * a.rho_c * sqrt(dzs);
+    const double br = fabs(a.scal[6]);
+    const int it = (int)a.scal[5];
+    a.scal[2] = pr;
+    a.scal[3] = dr;
+    a.scal[4] = br;
+    a.scal[5] = (double)(it + 1);
+    if (it < a.hist_cap) {
+      a.hist[3 * (int64_t)it + 0] = pr;
+      a.hist[3 * (int64_t)it + 1] = dr;
+      a.hist[3 * (int64_t)it + 2] = br;
+    }
+    if (!isfinite(pr)) atomicExch(a.status, 1);
+  }
+}
+
 hipError_t launch_global(const GlobalArgs& a, hipStream_t s) {
   if (a.C < 1) return hipErrorInvalidValue;
+  if (!a.split) {
+    hipLaunchKernelGGL(global_kernel, dim3(1), dim3(GT), 0, s, a);
+    return hipGetLastError();
+  }
+  if (a.G != global_groups(a.n) || a.G2 != global_groups2(a.n, a.C) || !a.gp)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(consensus_kernel, dim3(a.G), dim3(256), 0, s, a);
   hipLaunchKernelGGL(global_kernel, dim3(1), dim3(GT), 0, s, a);
+  hipLaunchKernelGGL(uresid_kernel, dim3(a.G2, a.N + 1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(gfinal_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -174,8 +174,51 @@ __device__ void topk_apply(const Z* z, int64_t n, uint64_t thr, int take_eq, Top
   }
 }
 
+// Consensus average of row k and the breakpoint data of the vector (z,t)
+// problem for it; adds d_k |wbar_k| to *s1 and raises *thmax to theta_k when finite.
+__device__ __forceinline__ void consensus_row(const GlobalArgs& a, int k, double* s1, double* thmax,
+                                              bool* bad) {
+  const int n = a.n, N = a.N, C = a.C;
+  const int64_t nc = (int64_t)n * C;
+  double* wbar = a.work;
+  double* zprev = a.work + nc;
+  double* rv = a.work + 2 * nc;
+  double* th = rv + n;
+  double* c1 = th + n;
+  double* c2 = c1 + n;
+  const double aa = N * a.rho_c;
+  double nrm2 = 0.0, w1 = 0.0;
+  for (int c = 0; c < C; ++c) {
+    const int64_t e = (int64_t)k * C + c;
+    zprev[e] = a.z[e];
+    double sacc = 0.0;
+    for (int i = 0; i < N; ++i) sacc += a.x[(int64_t)i * nc + e] + a.u[(int64_t)i * nc + e];
+    const double w = sacc / N;
+    wbar[e] = w;
+    nrm2 += w * w;
+    w1 = w;
+  }
+  const double w = C == 1 ? w1 : sqrt(nrm2);
+  *bad |= !isfinite(w);
+  rv[k] = w;
+  const double sg = w > 0.0 ? 1.0 : (w < 0.0 ? -1.0 : 0.0);
+  const double d = 1.0 - sg * a.s[k];
+  const double aw = fabs(w);
+  c1[k] = d * aw;
+  c2[k] = d * d / aa;
+  const double t = d > 0.0 ? aa * aw / d : INFINITY;
+  th[k] = t;
+  *s1 += d * aw;
+  if (t < INFINITY) *thmax = fmax(*thmax, t);
+}
+
 // One global step with a workgroup of BT threads, PS interior points per
 // multisection round; shd holds (BT / 64) * (PSECT + 2) doubles of shared memory.
+// With a.split the O(N n) parts run in their own many-workgroup kernels: the
+// consensus pass before (this step then only adds its per-workgroup partial
+// sums, a.gp[0 .. G) and maxima a.gp[G .. 2G)), and the u-update with the
+// residuals after (this step then leaves t, v and z^T s - t in scal[0], scal[1],
+// scal[6]).
 template <int BT, int PS = PSECT>
 __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tks) {
   constexpr int GT = BT;
@@ -194,33 +237,16 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
 
   // consensus average and breakpoint data of the vector (z,t) problem
   double s1loc = 0.0, thmax = 0.0;
-  bool bad = false;
-  for (int k = tid; k < n; k += GT) {
-    double nrm2 = 0.0, w1 = 0.0;
-    for (int c = 0; c < C; ++c) {
-      const int64_t e = (int64_t)k * C + c;
-      zprev[e] = a.z[e];
-      double sacc = 0.0;
-      for (int i = 0; i < N; ++i) sacc += a.x[(int64_t)i * nc + e] + a.u[(int64_t)i * nc + e];
-      const double w = sacc / N;
-      wbar[e] = w;
-      nrm2 += w * w;
-      w1 = w;
+  if (a.split) {
+    for (int g = tid; g < a.G; g += GT) {
+      s1loc += a.gp[g];
+      thmax = fmax(thmax, a.gp[a.G + g]);
     }
-    const double w = C == 1 ? w1 : sqrt(nrm2);
-    bad |= !isfinite(w);
-    rv[k] = w;
-    const double sg = w > 0.0 ? 1.0 : (w < 0.0 ? -1.0 : 0.0);
-    const double d = 1.0 - sg * a.s[k];
-    const double aw = fabs(w);
-    c1[k] = d * aw;
-    c2[k] = d * d / aa;
-    const double t = d > 0.0 ? aa * aw / d : INFINITY;
-    th[k] = t;
-    s1loc += d * aw;
-    if (t < INFINITY) thmax = fmax(thmax, t);
+  } else {
+    bool bad = false;
+    for (int k = tid; k < n; k += GT) consensus_row(a, k, &s1loc, &thmax, &bad);
+    if (bad) atomicExch(a.status, 1);
   }
-  if (bad) atomicExch(a.status, 1);
   const double S1all = block_sum<BT>(s1loc, shd);
   const double hi0 = block_max<BT>(thmax, shd);
 
@@ -383,6 +409,15 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
   });
   const double g = block_sum<BT>(gl, shd) - t;
   const double vn = v + g;
+  if (a.split) {
+    if (tid == 0) {
+      a.scal[0] = t;
+      a.scal[1] = vn;
+      a.scal[6] = g;
+      if (!isfinite(t) || !isfinite(vn)) atomicExch(a.status, 1);
+    }
+    return;
+  }
 
   // u-update and residuals (Frobenius norms for C > 1)
   double dz = 0.0;

@@ -992,15 +992,16 @@ int bca_set_vector(bca_problem P, int32_t which, int32_t part, const double* in)
   return BCA_OK;
 }
 
-// State blob: header, then x, u, z, s, (t, v), omega, nu, residual history.
+// State blob: header (with t, v, the residuals, the iteration count and the
+// last root theta of the (z,t) step), then x, u, z, s, omega, nu, residual history.
 struct StateHeader {
   uint64_t magic;
   int32_t n, C, N, kappa;
   int64_t m_total;
   int32_t iter, hist_cap;
-  double scal[6];
+  double scal[8];
 };
-static const uint64_t kStateMagic = 0x4243414453544131ull;  // "BCADSTA1"
+static const uint64_t kStateMagic = 0x4243414453544132ull;  // "BCADSTA2"
 
 int bca_get_state(bca_problem P, void* buf, size_t* bytes) {
   if (!P || !bytes) return fail(BCA_E_INVALID, "null argument");

@@ -245,7 +245,8 @@ struct GlobalArgs {
   double* u;               // N x n x C
   double* z;               // n x C
   double* s;               // n
-  double* scal;            // [0] t, [1] v, [2] pr, [3] dr, [4] br, [5] iter (as double)
+  double* scal;            // [0] t, [1] v, [2] pr, [3] dr, [4] br, [5] iter (as double),
+                           // [6] z^T s - t (split form), [7] last root theta of the (z,t) step
   double* hist;            // hist_cap x 3
   int32_t* support;        // kappa
   double* work;            // scratch: (2 C + 5) n doubles

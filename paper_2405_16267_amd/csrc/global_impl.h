@@ -262,8 +262,9 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
     // stay left of it and move monotonically to it; a step is the root of the
     // linear piece active right of the current point, theta' = (sum_A c1 - v) /
     // (1/rho_b + sum_A c2) with A = {k : theta_k > theta}, and it is exact once A
-    // no longer changes.  Newton starts at theta = 0 (psi(0) < 0 here); if it has
-    // not settled after 32 steps, multisection finishes the bracket from there.
+    // no longer changes.  Newton starts at theta = 0 (psi(0) < 0 here) or at the
+    // previous root; if it has not settled after 32 steps, multisection finishes
+    // the bracket from there.
     double lo = 0.0, hi = hi0;
     bool isolated = false;
     auto multisect = [&](int max_rounds) {
@@ -317,7 +318,21 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
     bool done = false;
     if (!isolated) {
       double cur = lo, sm[3];
-      active(cur, sm);
+      // warm start from the previous outer iteration's root tw: if psi(tw) <= 0
+      // Newton starts there (the root is the same exact value from any start
+      // left of it); otherwise tw bounds the root from above
+      const double tw = a.scal[7];
+      bool warm = false;
+      if (tw > 0.0 && tw < hi) {
+        active(tw, sm);
+        if (v + tw / rb + tw * sm[1] - sm[0] <= 0.0) {
+          cur = lo = tw;
+          warm = true;
+        } else {
+          hi = tw;
+        }
+      }
+      if (!warm) active(cur, sm);
       for (int it = 0; it < 32 && !done; ++it) {
         double nx = (sm[0] - v) / (1.0 / rb + sm[1]);
         nx = fmin(fmax(nx, cur), hi);
@@ -352,6 +367,7 @@ __device__ void global_step(const GlobalArgs& a, double* shd, TopkShared<BT>& tk
       theta = fmin(fmax(theta, lo), hi);
     }
   }
+  if (tid == 0) a.scal[7] = theta;   // the next step's warm start
   // z(theta) per row; rows of the matrix variable are scaled copies of wbar_k
   double tl = 0.0;
   for (int k = tid; k < n; k += GT) {

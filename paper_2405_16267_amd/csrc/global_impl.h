@@ -93,17 +93,22 @@ struct TopkShared {
   unsigned int hist[256];
   uint64_t prefix;
   int need;
+  int done;
   int scan[BT / 64 + 1];
 };
 
 // Select T_kappa of |z| (z of type Z, n entries): returns the threshold key and,
 // through *take_eq, how many entries equal to it are kept (lowest indices).
+// Digit passes stop once the chosen bin holds exactly the entries still needed:
+// the whole bin is then kept, with the threshold at the bin's lowest key pattern
+// (the same set the remaining passes would select).
 template <int BT, typename Z>
 __device__ uint64_t topk_threshold(const Z* z, int64_t n, int kappa, TopkShared<BT>& sh, int* take_eq) {
   constexpr int GT = BT;
   constexpr int BITS = sizeof(Z) * 8;
   uint64_t prefix = 0, mask = 0;
   int need = kappa;
+  if (threadIdx.x == 0) sh.done = 0;
   for (int d = BITS - 8; d >= 0; d -= 8) {
     for (int b = threadIdx.x; b < 256; b += GT) sh.hist[b] = 0;
     __syncthreads();
@@ -135,13 +140,16 @@ __device__ uint64_t topk_threshold(const Z* z, int64_t n, int kappa, TopkShared<
         }
         sh.prefix = prefix | ((uint64_t)D << d);
         sh.need = need - cum;
+        sh.done = (need - cum) == (int)sh.hist[D];
       }
     }
     __syncthreads();
     prefix = sh.prefix;
     need = sh.need;
     mask |= (uint64_t)255 << d;
+    const bool whole_bin = sh.done != 0;
     __syncthreads();
+    if (whole_bin) break;
   }
   *take_eq = need;
   return prefix;

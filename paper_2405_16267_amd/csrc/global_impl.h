@@ -101,7 +101,8 @@ struct TopkShared {
 // through *take_eq, how many entries equal to it are kept (lowest indices).
 // Digit passes stop once the chosen bin holds exactly the entries still needed:
 // the whole bin is then kept, with the threshold at the bin's lowest key pattern
-// (the same set the remaining passes would select).
+// (the same set the remaining passes would select); with fewer than kappa
+// nonzero entries the first pass ends the walk at threshold 0.
 template <int BT, typename Z>
 __device__ uint64_t topk_threshold(const Z* z, int64_t n, int kappa, TopkShared<BT>& sh, int* take_eq) {
   constexpr int GT = BT;
@@ -112,9 +113,21 @@ __device__ uint64_t topk_threshold(const Z* z, int64_t n, int kappa, TopkShared<
   for (int d = BITS - 8; d >= 0; d -= 8) {
     for (int b = threadIdx.x; b < 256; b += GT) sh.hist[b] = 0;
     __syncthreads();
+    int nzl = 0;
     for (int64_t k = threadIdx.x; k < n; k += GT) {
       const uint64_t key = abs_key(z[k]);
+      nzl += key != 0;
       if ((key & mask) == prefix) atomicAdd(&sh.hist[(key >> d) & 255u], 1u);
+    }
+    if (d == BITS - 8) {
+      // fewer than kappa nonzero entries: the threshold is 0 and the
+      // lowest-index zeros fill T_kappa, which is where the digit walk would end
+      int nz;
+      (void)block_exscan<BT>(nzl, sh.scan, &nz);
+      if (nz < kappa) {
+        *take_eq = kappa - nz;
+        return 0;
+      }
     }
     __syncthreads();
     if (threadIdx.x < 64) {

@@ -89,6 +89,11 @@ def test_topk_bit_exact_on_ties():
     cases += [(v, 1), (v, 50), (v, 2500), (v, 4999), (v, 5000)]
     v2 = r.standard_normal(70000)
     cases += [(v2, 1000)]
+    # mostly zeros: fewer nonzero entries than kappa (threshold 0, lowest-index zeros
+    # kept), exactly kappa nonzero entries, and one fewer
+    v3 = np.zeros(60000)
+    v3[r.choice(60000, 1000, replace=False)] = r.standard_normal(1000)
+    cases += [(v3, 3000), (v3, 1000), (v3, 999), (v3, 1001)]
     for z, k in cases:
         ref = oracle.topk_support(z, k)
         for dt in (torch.float64, torch.float32):

@@ -41,3 +41,34 @@ def test_params_struct_layout_matches_header():
 
 def test_last_error_is_empty_string_initially():
     assert isinstance(bca.lib().bca_last_error(), bytes)
+
+
+def header_enums():
+    """Every BCA_* enumerator of include/bca.h with its value."""
+    src = open(os.path.join(ROOT, "include", "bca.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"\b(BCA_\w+)\s*=\s*(-?\d+)", body):
+            vals[name] = int(val)
+    return vals
+
+
+def test_binding_constants_match_header_enums():
+    from paper_2405_16267_amd import bca as b
+    h = header_enums()
+    assert h["BCA_OK"] == b.BCA_OK
+    for code, name in b.ERRORS.items():
+        assert h[name] == code, name
+    for name, v in b.LOSS.items():
+        assert h["BCA_LOSS_" + name.upper()] == v
+    for name, v in b.DTYPE.items():
+        assert h["BCA_" + name.upper()] == v
+    assert (h["BCA_MEM_HOST"], h["BCA_MEM_DEVICE"]) == (b.MEM_HOST, b.MEM_DEVICE)
+    assert (h["BCA_FLAG_EXACT_X"], h["BCA_FLAG_WOODBURY"]) == (b.FLAG_EXACT_X, b.FLAG_WOODBURY)
+    for name in ("X", "U", "Z", "S", "OMEGA", "NU", "TV"):
+        assert h["BCA_VEC_" + name] == getattr(bca, "VEC_" + name), name
+    for name in ("STREAM", "SOLVE", "GLOBAL", "GRAM", "FACTOR"):
+        assert h["BCA_KC_" + name] == getattr(bca, "KC_" + name), name
+    for name in ("QUEUED", "RUNNING", "DONE", "FAILED", "CANCELLED"):
+        assert h["BCA_REQ_" + name] == getattr(b, "REQ_" + name), name

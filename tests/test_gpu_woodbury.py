@@ -207,3 +207,30 @@ def test_woodbury_all_zero_data_stays_at_zero():
     assert (pr, dr, br, it) == (0.0, 0.0, 0.0, 5)
     assert np.array_equal(P.support(), np.arange(5))   # ties go to the lowest indices
     P.close()
+
+
+def test_woodbury_full_size_matches_default_form():
+    """The benchmark shape of the sample-space form (8 partitions of 800 x 10,000
+    FP32, one block, kappa = 2,000), where the oracle's 10,000 x 10,000 factors are
+    too slow for a test: against the default form on the GPU, a property that
+    holds at any size (the two forms compute the same iterates up to rounding)."""
+    bca = _bca()
+    N, m, n, kappa = 8, 800, 10000, 2000
+    supp, val = datagen.linear_model(31, n, kappa)
+    probs = []
+    for wb in (True, False):
+        P = bca.Problem("squared", n, [m] * N, 1, kappa, dtype="f32", max_iters=10, woodbury=wb)
+        for i in range(N):
+            A, b = datagen.linear_partition(31, i, m, n, supp, val, 0.05, "f32", True)
+            P.set_data(i, A, b)
+        P.finalize()
+        P.step(10)
+        probs.append(P)
+    W, D = probs
+    assert rel(D.get_vector(bca.VEC_Z), W.get_vector(bca.VEC_Z)) < 1e-5
+    for i in (0, N - 1):
+        assert rel(D.get_vector(bca.VEC_X, i), W.get_vector(bca.VEC_X, i)) < 1e-5
+    hw, hd = W.history(), D.history()
+    assert np.allclose(hw, hd, rtol=1e-3, atol=1e-6)
+    for P in probs:
+        P.close()

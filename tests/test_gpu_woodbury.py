@@ -234,3 +234,23 @@ def test_woodbury_full_size_matches_default_form():
     assert np.allclose(hw, hd, rtol=1e-3, atol=1e-6)
     for P in probs:
         P.close()
+
+
+@pytest.mark.parametrize("woodbury", [False, True])
+def test_rho_b_study_regime_f64(woodbury):
+    """The recipe of the paper's rho_b study (unit-norm columns, kappa = 0.2 n planted
+    nonzeros) at its largest penalties, rho_b = 16 and rho_c = rho_l = 32, on a size
+    the oracle finishes in seconds (4 partitions of 90 rows, n = 200, one block, so
+    m_i < n_j): the default and the sample-space x-step against the oracle after
+    every outer iteration."""
+    w = datagen.linear_workload(21, N=4, m_per=[90, 90, 90, 90], n=200, kappa=40, k_true=40,
+                                noise=0.05, n_blocks=1, dtype="f64", normalize=True, max_iters=8,
+                                rho=32.0)
+    w.rho_b = 16.0
+    P = make(w, woodbury=woodbury)
+    o = make_oracle(w)
+    for _ in range(w.max_iters):
+        P.step(1)
+        o.iterate(1, w.inner_iters)
+        _state_matches(P, o, w, 1e-10)
+    P.close()

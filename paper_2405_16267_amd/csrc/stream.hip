@@ -251,7 +251,8 @@ __global__ __launch_bounds__(NT) void objective_kernel(ObjArgs a) {
 // per chunk, so x and the FP64 sums take more registers per streamed byte, and
 // the next tile is prefetched): maxc 4, 4 rows per tile, or 2 rows per tile when
 // the environment variable BCA_BF16_STREAM_ROWS is 2 (measured at 16 x 100,000 x
-// 10,000: 5.66 TB/s with 4 rows, 4.97 TB/s with 2).
+// 10,000: 5.66 TB/s with 4 rows, 4.97 TB/s with 2); BF16 rows of 1,025-1,344 chunks
+// with 4 rows per tile take 448 threads x 3 chunks.
 struct StreamShape {
   int nt, nc, r;
 };
@@ -279,6 +280,9 @@ static StreamShape stream_shape(int nvec) {
   int c = (nvec + sh.nt - 1) / sh.nt;
   if (c == 7) c = 8;
   sh.nc = c < 1 ? 1 : c;
+  // BF16 rows of 1,025-1,344 chunks: 448 threads x 3 chunks leave fewer idle
+  // chunk slots than 512 x 3 (10,000-column rows: 5.99 against 5.86 TB/s)
+  if (Traits<T>::VEC == 8 && sh.r == 4 && sh.nt == 512 && sh.nc == 3 && nvec <= 3 * 448) sh.nt = 448;
   return sh;
 }
 
@@ -313,6 +317,9 @@ static auto with_shape(const StreamShape& sh, F f) {
     }
   }
   if (sh.nt == 256) BCA_NC(256, 4)
+  if constexpr (Traits<T>::VEC == 8) {
+    if (sh.nt == 448) return f.template run<448, 3, 4>();
+  }
   if (sh.nt == 512) BCA_NC(512, 4)
   BCA_NC(1024, 4)
 #undef BCA_NC
@@ -385,7 +392,7 @@ static hipError_t objective_dispatch(const ObjArgs& a, hipStream_t s) {
       case 6: BCA_OBJ(256, 6); break;
       default: BCA_OBJ(256, 8); break;
     }
-  } else if (nt == 512) {
+  } else if (nt == 512 || nt == 448) {  // 448: the BF16 shape of 1,025-1,344 chunks
     switch (nc) {
       case 1: BCA_OBJ(512, 1); break;
       case 2: BCA_OBJ(512, 2); break;

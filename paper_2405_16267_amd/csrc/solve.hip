@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256) void reduce_rhs_kernel(SolveArgs a) {
   a.rhs[o] = a.rho_l * ate + a.rho_c * (a.z[k] - a.u[o]) - a.shift * a.x[o];
 }
 
+template <bool NTL>
 __global__ __launch_bounds__(256) void symv_kernel(SolveArgs a) {
   const int bid = blockIdx.y;
   const int part = bid / a.M, blk = bid - part * a.M;
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void symv_kernel(SolveArgs a) {
   int I, J;
   tri_tile(t, &I, &J);
   const int T = (nj + PT - 1) / PT, tmax = (a.nj_max + PT - 1) / PT;
-  symv_tile(a.kinv + a.fac_off[bid] + (int64_t)t * PT_ELEMS, a.rhs + ((int64_t)part * a.n + c0) * a.C,
+  symv_tile<NTL>(a.kinv + a.fac_off[bid] + (int64_t)t * PT_ELEMS, a.rhs + ((int64_t)part * a.n + c0) * a.C,
             nj, a.C, I, J, T, a.ypart + (int64_t)bid * tmax * tmax * PT * a.C);
 }
 
@@ -79,13 +80,28 @@ __global__ __launch_bounds__(256) void xupd_kernel(SolveArgs a) {
     reinterpret_cast<float*>(a.xs)[so] = (float)xn;
 }
 
+// The symmetric products of all blocks.  ntl: tiles beyond 1 GB in all are read
+// with nontemporal loads.  Only the exact x-update asks for it: there nothing but
+// these products touches HBM (6.4 GB of tiles at 16 x 10,000: 1.29 -> 1.19 ms),
+// while with Algorithm 2's streaming pass between the products the nontemporal
+// tiles made that pass slower (FP32 at 16 x 100,000 x 10,000: 9.25 -> 9.84 ms
+// per launch, measured A/B in one job) and 220 MB of tiles read faster with
+// ordinary loads.
+static void symv_launch(const SolveArgs& a, hipStream_t s, bool ntl) {
+  const int64_t tiles = ptile_count(a.nj_max);
+  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
+  const double bytes = (double)tiles * PT_ELEMS * 8.0 * a.N * a.M;
+  if (ntl && bytes > (double)(1ll << 30))
+    hipLaunchKernelGGL(symv_kernel<true>, g2, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(symv_kernel<false>, g2, dim3(256), 0, s, a);
+}
+
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
   if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
   dim3 g1((unsigned)(((int64_t)a.n * a.C + 255) / 256), a.N);
   hipLaunchKernelGGL(reduce_rhs_kernel, g1, dim3(256), 0, s, a);
-  const int64_t tiles = ptile_count(a.nj_max);
-  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
-  hipLaunchKernelGGL(symv_kernel, g2, dim3(256), 0, s, a);
+  symv_launch(a, s, false);
   dim3 g3((unsigned)(((int64_t)a.nj_max * a.C + 255) / 256), a.N * a.M);
   hipLaunchKernelGGL(xupd_kernel<false>, g3, dim3(256), 0, s, a);
   return hipGetLastError();
@@ -93,9 +109,7 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t s) {
 
 hipError_t launch_symv(const SolveArgs& a, hipStream_t s) {
   if (a.C < 1 || a.C > 16) return hipErrorInvalidValue;
-  const int64_t tiles = ptile_count(a.nj_max);
-  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
-  hipLaunchKernelGGL(symv_kernel, g2, dim3(256), 0, s, a);
+  symv_launch(a, s, false);
   return hipGetLastError();
 }
 
@@ -121,9 +135,7 @@ hipError_t launch_solve_exact(const SolveArgs& a, hipStream_t s) {
   if (a.C != 1 || a.M != 1) return hipErrorInvalidValue;
   dim3 g1((unsigned)((a.n + 255) / 256), a.N);
   hipLaunchKernelGGL(exact_rhs_kernel, g1, dim3(256), 0, s, a);
-  const int64_t tiles = ptile_count(a.nj_max);
-  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
-  hipLaunchKernelGGL(symv_kernel, g2, dim3(256), 0, s, a);
+  symv_launch(a, s, true);
   dim3 g3((unsigned)((a.nj_max + 255) / 256), a.N * a.M);
   hipLaunchKernelGGL(xupd_kernel<true>, g3, dim3(256), 0, s, a);
   return hipGetLastError();

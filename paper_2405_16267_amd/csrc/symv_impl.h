@@ -20,7 +20,10 @@ typedef double symv_d2 __attribute__((ext_vector_type(2)));
 // feature-major); ys: the block's slots, slot (R, S) at ys + (R T + S) 64 C.
 // Lane l = 8 a + b holds rows 16 q + 2 a + h (q < 4, h < 2) and columns
 // 8 b .. 8 b + 7 of the tile.  Row sums are reduced over the 8 lanes of equal a
-// (DPP), column sums over the 8 lanes of equal b.
+// (DPP), column sums over the 8 lanes of equal b.  NTL: nontemporal tile loads,
+// for tile sets far larger than the last-level cache (smaller ones are partly
+// still cached from the previous product).
+template <bool NTL = false>
 __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const double* __restrict__ r,
                                           int nj, int C, int I, int J, int T, double* __restrict__ ys) {
   const int lane = threadIdx.x & 63;
@@ -31,7 +34,12 @@ __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) p[q][k] = tp[(q * 8 + k) * 64];
+    for (int k = 0; k < 8; ++k) {
+      if constexpr (NTL)
+        p[q][k] = __builtin_nontemporal_load(tp + (q * 8 + k) * 64);
+      else
+        p[q][k] = tp[(q * 8 + k) * 64];
+    }
   const int colJ = PT * J + 8 * b, rowI = PT * I + 2 * a;
   for (int c = 0; c < C; ++c) {
     // indices past n_j are clamped: the tile is zero there

@@ -469,3 +469,122 @@ def test_objective_definition():
     bl = [np.array([1.0]), np.array([-1.0])]
     expect = math.log1p(math.exp(-3.0)) + math.log1p(math.exp(-1.0)) + 0.5
     assert abs(oracle.objective(LOSS_LOGISTIC, A, bl, x, 2.0) - expect) < 1e-15
+
+
+def test_objective_worked_examples_softmax_and_hinge():
+    """Objective of Sec. 2 for the softmax loss (row sparsity, classes from 0) and the
+    hinge loss of the sparse SVM, against hand-worked values in tests/golden: a wrong
+    class index, LSE replaced by the max, a dropped max(0, .) or a flipped label sign
+    each changes the value."""
+    ex = json.load(open(os.path.join(GOLDEN, "loss_worked_examples.json")))["examples"]
+    for e in ex:
+        A = [np.array(a, dtype=float) for a in e["A"]]
+        if e["loss"] == "softmax":
+            loss = LOSS_SOFTMAX
+            b = [np.array(y, dtype=np.int32) for y in e["b"]]
+        else:
+            loss = LOSS_HINGE
+            b = [np.array(y, dtype=float) for y in e["b"]]
+        x = np.array(e["x"], dtype=float)
+        ls = sum(oracle.loss_value(loss, Ai @ x, bi) for Ai, bi in zip(A, b))
+        assert abs(ls - e["loss_sum"]) <= 4e-16 * abs(e["loss_sum"]), (e["loss"], ls)
+        f = oracle.objective(loss, A, b, x, e["gamma"])
+        assert abs(f - e["objective"]) <= 4e-16 * abs(e["objective"]), (e["loss"], f)
+
+
+def _zt_matrix_generic(W, s, v, a, rb, rng, starts=6):
+    """Generic solver of the row-sparse (z, t) problem of the softmax model:
+        min_{Z, t}  (a/2)||Z - W||_F^2 + (rb/2)(sum_r s_r ||Z_r|| - t + v)^2
+        s.t.        sum_r ||Z_r|| <= t,
+    written without the reduction to row norms.  The row norms are not smooth at
+    Z_r = 0, so every subset P of rows is tried as the set of nonzero rows (the
+    others fixed at 0), each smooth problem by SLSQP from several starts; the best
+    feasible point over all subsets is returned."""
+    n, C = W.shape
+    best = (np.inf, None, None)
+    for mask in itertools.product([False, True], repeat=n):
+        P = [r for r in range(n) if mask[r]]
+        k = len(P)
+        Wz = float(np.sum(W[[r for r in range(n) if not mask[r]]] ** 2))
+
+        def unpack(y):
+            return y[:k * C].reshape(k, C), y[k * C]
+
+        def f(y):
+            Z, t = unpack(y)
+            nr = np.sqrt(np.sum(Z * Z, axis=1))
+            res = float(s[P] @ nr) - t + v
+            return 0.5 * a * (np.sum((Z - W[P]) ** 2) + Wz) + 0.5 * rb * res * res
+
+        def g(y):
+            Z, t = unpack(y)
+            nr = np.maximum(np.sqrt(np.sum(Z * Z, axis=1)), 1e-300)
+            res = float(s[P] @ nr) - t + v
+            gz = a * (Z - W[P]) + rb * res * (s[P] / nr)[:, None] * Z
+            return np.concatenate([gz.ravel(), [-rb * res]])
+
+        def cf(y):
+            Z, t = unpack(y)
+            return t - np.sum(np.sqrt(np.sum(Z * Z, axis=1)))
+
+        def cj(y):
+            Z, t = unpack(y)
+            nr = np.maximum(np.sqrt(np.sum(Z * Z, axis=1)), 1e-300)
+            return np.concatenate([(-Z / nr[:, None]).ravel(), [1.0]])
+
+        for st in range(starts if k else 1):
+            if st == 0:
+                Z0 = W[P] + (np.abs(W[P]) < 1e-12) * 1e-3
+            else:
+                Z0 = rng.standard_normal((k, C)) * (1.0 + np.abs(W[P]))
+            y0 = np.concatenate([Z0.ravel(), [np.sum(np.sqrt(np.sum(Z0 * Z0, axis=1))) + 1.0]])
+            res = minimize(f, y0, jac=g, constraints=[dict(type="ineq", fun=cf, jac=cj)],
+                           method="SLSQP", options=dict(ftol=1e-16, maxiter=2000))
+            y = res.x
+            if cf(y) < -1e-10:
+                continue
+            fy = f(y)
+            if fy < best[0]:
+                Z = np.zeros((n, C))
+                Z[P] = unpack(y)[0]
+                best = (fy, Z, unpack(y)[1])
+    return best
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_softmax_row_sparse_zt_step_is_the_matrix_minimiser(seed):
+    """Row-sparse (z, t) step of the softmax model (reading: Hempel's theorem on the row
+    norms of X, Sec. 2.1, with the (z, t) minimisation of the ADMM iterations, Sec. 3),
+    run through the oracle's global step with kappa < n, against a generic solver of the
+    matrix problem that does not use the reduction to row norms."""
+    r = _rng(700 + seed)
+    N, n, C = 2, int(r.integers(2, 5)), int(r.integers(2, 4))
+    kappa = int(r.integers(1, n))
+    rc, rb = float(r.uniform(0.5, 2.0)), float(r.uniform(0.3, 2.0))
+    A = [np.zeros((1, n)) for _ in range(N)]
+    b = [np.zeros(1, dtype=np.int32) for _ in range(N)]
+    o = oracle.BiCADMM(A, b, LOSS_SOFTMAX, 1, kappa, 10.0, rc, rb, 1.0, n_classes=C)
+    st = o.state
+    st.x = r.standard_normal((N, n, C))
+    st.u = 0.5 * r.standard_normal((N, n, C))
+    if seed % 3 == 0:                      # a zero row of the consensus target
+        st.x[:, 0, :] = 0.0
+        st.u[:, 0, :] = 0.0
+    s = r.uniform(-1.0, 1.0, n)
+    if seed % 4 == 1:
+        s = np.abs(s)                      # the s-step's own sign pattern on row norms
+    if seed % 5 == 2:
+        s[:] = 0.0
+    st.s = s.copy()
+    v = float(r.standard_normal()) * (3.0 if seed % 2 else 0.7)
+    st.v = v
+    W = np.mean(st.x + st.u, axis=0)
+    a = N * rc
+    o.global_update()
+    Z, t = st.z, st.t
+    nr = np.sqrt(np.sum(Z * Z, axis=1))
+    assert np.sum(nr) <= t + 1e-12
+    fo = 0.5 * a * np.sum((Z - W) ** 2) + 0.5 * rb * (s @ nr - t + v) ** 2
+    fg, Zg, tg = _zt_matrix_generic(W, s, v, a, rb, _rng(900 + seed))
+    assert fo <= fg + 1e-10 * max(1.0, abs(fg)), (fo, fg)
+    assert np.max(np.abs(Z - Zg)) < 1e-4 and abs(t - tg) < 1e-4, (np.max(np.abs(Z - Zg)), t, tg)

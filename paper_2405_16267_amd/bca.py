@@ -6,8 +6,10 @@ not been built; there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -106,6 +108,22 @@ def _load():
 
 _lib = _load()
 
+# Handles still open when the interpreter exits are released by an exit hook that
+# runs before module teardown, while the HIP runtime (and any profiler attached to
+# it) is still up: Problem.__del__ / Server.__del__ during interpreter finalisation
+# would otherwise call into the runtime in an unspecified order with its own exit
+# handlers (the server's scheduler thread would still be running).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
 
 def lib():
     return _lib
@@ -158,6 +176,7 @@ class Problem:
         h = ctypes.c_void_p()
         _check(_lib.bca_create(ctypes.byref(p), self._stream, ctypes.byref(h)))
         self._h = h
+        _LIVE.add(self)
 
     # -- lifecycle
     def close(self):
@@ -344,6 +363,7 @@ class Server:
         _check(_lib.bca_server_create(hbm_budget_bytes, max_slots, round_iters, st, ctypes.byref(h)))
         self._h = h
         self._meta = {}
+        _LIVE.add(self)
 
     def submit(self, loss: str, A_parts, b_parts, n_blocks: int, kappa: int, gamma=10.0,
                rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5, max_iters=100, dtype="f32",

@@ -481,6 +481,13 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     return fail(BCA_E_INVALID, "the exact x-update needs the squared loss");
   for (int i = 0; i < p.n_partitions; ++i)
     if (p.rows[i] < 1) return fail(BCA_E_INVALID, "rows[%d] must be >= 1", i);
+  {
+    const int vec = p.a_dtype == BCA_F64 ? 2 : (p.a_dtype == BCA_F32 ? 4 : 8);
+    const int64_t nv = ((int64_t)p.n_features + vec - 1) / vec;
+    if (C == 1 && nv > kStreamMaxVec)
+      return fail(BCA_E_INVALID, "n_features %d exceeds the widest streaming row (%d for this a_dtype)",
+                  p.n_features, kStreamMaxVec * vec);
+  }
 
   bca_problem P = new bca_problem_s();
   P->p = p;
@@ -1049,6 +1056,12 @@ int bca_set_state(bca_problem P, const void* buf, size_t bytes) {
   if (h.magic != kStateMagic || h.n != P->n || h.C != P->C || h.N != P->N || h.kappa != P->kappa ||
       h.m_total != P->m_total || h.hist_cap != P->p.max_iters || bytes < need)
     return fail(BCA_E_INVALID, "state blob does not match this problem");
+  // the iteration count indexes the residual history on the device (rows past
+  // max_iters are not recorded, so bca_step may have taken it beyond max_iters)
+  if (h.iter < 0 || h.scal[5] != (double)h.iter)
+    return fail(BCA_E_INVALID, "state blob: iteration count %d negative or inconsistent", h.iter);
+  for (int k = 0; k < 8; ++k)
+    if (!std::isfinite(h.scal[k])) return fail(BCA_E_INVALID, "state blob: non-finite scalar %d", k);
   const double* d = reinterpret_cast<const double*>(reinterpret_cast<const char*>(buf) + sizeof(StateHeader));
   HIP_TRY(hipMemcpyAsync(P->scal, h.scal, sizeof(h.scal), hipMemcpyHostToDevice, P->stream));
   HIP_TRY(hipMemcpyAsync(P->x, d, P->N * nx * 8, hipMemcpyHostToDevice, P->stream)); d += P->N * nx;

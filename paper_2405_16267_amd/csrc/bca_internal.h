@@ -158,6 +158,9 @@ bool mc_supported(int n, int C);
 hipError_t launch_stream_mc(const StreamArgs& a, int dtype, hipStream_t s);
 hipError_t launch_objective_mc(const ObjArgs& a, int dtype, hipStream_t s);
 int stream_occupancy_workgroups(int dtype, int nvec, int C);   // resident workgroups per CU
+// Widest row of the one-class streaming and objective passes, in 16-byte chunks:
+// 1,024 threads x 8 chunks (n <= 16,384 FP64, 32,768 FP32, 65,536 BF16).
+constexpr int kStreamMaxVec = 1024 * 8;
 
 struct GramArgs {
   const void* A;

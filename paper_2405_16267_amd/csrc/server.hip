@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -47,7 +48,7 @@ struct Request {
   std::vector<std::vector<char>> A, b;
   double t_submit = 0, t_admit = 0, t_done = 0;
   int state = RQ_QUEUED;
-  bool cancel = false;
+  std::atomic<bool> cancel{false};   // set by bca_server_cancel, read by the scheduler
   bca_problem prob = nullptr;
   size_t bytes = 0;
   std::vector<int32_t> support;

@@ -247,28 +247,18 @@ __global__ __launch_bounds__(NT) void objective_kernel(ObjArgs a) {
 // Launch shape of the streaming pass for rows of nvec 16-byte chunks: threads per
 // workgroup, chunks per thread and rows per tile.  Up to `maxc` chunks per
 // thread with 256 threads, then 512 threads (still up to 256 VGPRs per lane),
-// then 1024.  FP32/FP64 rows: maxc 6, 4 rows per tile.  BF16 rows (8 columns
-// per chunk, so x and the FP64 sums take more registers per streamed byte, and
-// the next tile is prefetched): maxc 4, 4 rows per tile, or 2 rows per tile when
-// the environment variable BCA_BF16_STREAM_ROWS is 2 (measured at 16 x 100,000 x
-// 10,000: 5.66 TB/s with 4 rows, 4.97 TB/s with 2); BF16 rows of 1,025-1,344 chunks
-// with 4 rows per tile take 448 threads x 3 chunks.
+// then 1024, at most 8 chunks per thread (stream_max_chunks): FP32/FP64 rows
+// maxc 6, BF16 rows (8 columns per chunk, so x and the FP64 sums take more
+// registers per streamed byte, and the next tile is prefetched) maxc 4; 4 rows
+// per tile.  BF16 rows of 1,025-1,344 chunks take 448 threads x 3 chunks.
 struct StreamShape {
   int nt, nc, r;
 };
 
-static int bf16_rows() {
-  static int rows = [] {
-    const char* e = getenv("BCA_BF16_STREAM_ROWS");
-    return (e && atoi(e) == 2) ? 2 : 4;
-  }();
-  return rows;
-}
-
 template <typename T>
 static StreamShape stream_shape(int nvec) {
   StreamShape sh;
-  sh.r = Traits<T>::VEC == 8 ? bf16_rows() : 4;
+  sh.r = 4;
   const int maxc = Traits<T>::VEC == 8 ? 4 : 6;
   if (nvec <= maxc * 256) {
     sh.nt = 256;
@@ -282,7 +272,7 @@ static StreamShape stream_shape(int nvec) {
   sh.nc = c < 1 ? 1 : c;
   // BF16 rows of 1,025-1,344 chunks: 448 threads x 3 chunks leave fewer idle
   // chunk slots than 512 x 3 (10,000-column rows: 5.99 against 5.86 TB/s)
-  if (Traits<T>::VEC == 8 && sh.r == 4 && sh.nt == 512 && sh.nc == 3 && nvec <= 3 * 448) sh.nt = 448;
+  if (Traits<T>::VEC == 8 && sh.nt == 512 && sh.nc == 3 && nvec <= 3 * 448) sh.nt = 448;
   return sh;
 }
 
@@ -296,7 +286,8 @@ constexpr bool use_xl() {
   return Traits<T>::VEC == 8 && NC * Traits<T>::VEC * NT * 4 <= 128 * 1024;
 }
 
-// Calls F::template run<NT, NC, R>() for the shape (R in {2, 4}, 2 for BF16 only).
+// Calls F::template run<NT, NC, R>() for the shape (R = 4; sh.nc <= 8, which
+// bca_create guarantees through stream_max_chunks).
 template <typename T, typename F>
 static auto with_shape(const StreamShape& sh, F f) {
 #define BCA_NC(NT_, R_)                                  \
@@ -308,13 +299,6 @@ static auto with_shape(const StreamShape& sh, F f) {
     case 5: return f.template run<NT_, 5, R_>();         \
     case 6: return f.template run<NT_, 6, R_>();         \
     default: return f.template run<NT_, 8, R_>();        \
-  }
-  if constexpr (Traits<T>::VEC == 8) {
-    if (sh.r == 2) {
-      if (sh.nt == 256) BCA_NC(256, 2)
-      if (sh.nt == 512) BCA_NC(512, 2)
-      BCA_NC(1024, 2)
-    }
   }
   if (sh.nt == 256) BCA_NC(256, 4)
   if constexpr (Traits<T>::VEC == 8) {
@@ -350,6 +334,7 @@ struct StreamOcc {
 
 template <typename T>
 static hipError_t stream_dispatch(const StreamArgs& a, hipStream_t s) {
+  if (a.nvec < 1 || a.nvec > kStreamMaxVec) return hipErrorInvalidValue;
   return with_shape<T>(stream_shape<T>(a.nvec), StreamLaunch<T>{a, s});
 }
 
@@ -378,6 +363,7 @@ int stream_occupancy_workgroups(int dtype, int nvec, int C) {
 
 template <typename T>
 static hipError_t objective_dispatch(const ObjArgs& a, hipStream_t s) {
+  if (a.nvec < 1 || a.nvec > kStreamMaxVec) return hipErrorInvalidValue;
   const StreamShape sh = stream_shape<T>(a.nvec);
   const int nt = sh.nt, nc = sh.nc;
   dim3 grid(a.N * a.Gp);

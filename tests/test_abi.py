@@ -72,3 +72,21 @@ def test_binding_constants_match_header_enums():
         assert h["BCA_KC_" + name] == getattr(bca, "KC_" + name), name
     for name in ("QUEUED", "RUNNING", "DONE", "FAILED", "CANCELLED"):
         assert h["BCA_REQ_" + name] == getattr(b, "REQ_" + name), name
+
+
+def test_create_rejects_rows_wider_than_the_streaming_pass():
+    """One-class problems stream every row through one workgroup of at most 1,024
+    threads x 8 chunks of 16 bytes; wider rows are refused at create (argument
+    validation runs before any device call, so no GPU is needed)."""
+    import ctypes
+    from paper_2405_16267_amd import bca as b
+    for dtype, nmax in (("f64", 16384), ("f32", 32768), ("bf16", 65536)):
+        rows = (ctypes.c_int64 * 1)(10)
+        p = b.Params(loss=0, n_features=nmax + 1, n_classes=1, n_partitions=1, n_blocks=64, kappa=5,
+                     rows=rows, gamma=10.0, rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5,
+                     max_iters=10, tol_p=1e-6, tol_d=1e-6, tol_b=1e-6, a_dtype=b.DTYPE[dtype],
+                     check_every=10, flags=0)
+        h = ctypes.c_void_p()
+        rc = b.lib().bca_create(ctypes.byref(p), ctypes.c_void_p(None), ctypes.byref(h))
+        assert rc == -1 and not h.value, (dtype, rc)
+        assert b"widest streaming row" in b.lib().bca_last_error()

@@ -9,6 +9,7 @@ import pytest
 
 import datagen
 import oracle
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -29,11 +30,6 @@ def make(w):
         P.set_data(i, w.A[i], w.b[i])
     P.finalize()
     return P
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def mix(dtype="f32", K=12):
@@ -97,6 +93,49 @@ def test_batch_against_oracle_f64():
     P.close()
 
 
+# Every batched tile shape (chunks per lane NC, rows per tile R, segments per
+# wavefront S) forced on an FP32 instance whose row length selects it: S = 4 for
+# n <= 64, S = 2 for n <= 128, NC = 1, 2, 4, 8 up to n = 256, 512, 1024, 2048.
+SHAPE_CASES = [(60, R) for R in (1, 2, 4, 8)] + [(120, R) for R in (1, 2, 4, 8)] + \
+              [(250, R) for R in (1, 2, 4, 8)] + [(500, R) for R in (1, 2, 4)] + \
+              [(1000, R) for R in (1, 2)] + [(2000, 1)]
+
+
+def test_batch_every_tile_shape_against_oracle_f32():
+    """One persistent launch over 18 FP32 instances (squared and logistic), each
+    forced onto its own tile shape and rows per item (64, 256, 1024 in turn), against
+    the FP64 oracle: z element-wise at 1e-5, the support where the oracle's top-kappa
+    margin is clear of that, coefficients and objective at 1e-5 (reading R20)."""
+    bca = _bca()
+    K = 10
+    ws, P = [], []
+    for q, (n, R) in enumerate(SHAPE_CASES):
+        m = 2400 + 131 * q
+        w = datagen.batched_instance(40 + q, m, n, dtype="f32", max_iters=K)
+        p = make(w)
+        p.set_batch_shape(R, (64, 256, 1024)[q % 3])
+        assert p.batch_shape() == (R, (64, 256, 1024)[q % 3])
+        ws.append(w)
+        P.append(p)
+    bca.batch_step(P, K)
+    for w, p in zip(ws, P):
+        o = oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
+                           w.gamma, w.rho_c, w.rho_b, w.rho_l)
+        o.iterate(K, w.inner_iters)
+        z, oz = p.get_vector(bca.VEC_Z), o.state.z
+        inf = float(np.max(np.abs(oz)))
+        assert rel(z, oz) < 1e-5 and float(np.max(np.abs(z - oz))) <= 1e-5 * inf, (w.name, p.batch_shape())
+        if o.topk_margin() > 1e-3 * inf:
+            assert np.array_equal(p.support(), o.support()), w.name
+            assert_coef_close(p.coef(), o.coef(), 1e-5, w.name)
+            f, fo = p.objective(), o.objective(o.coef())
+            assert abs(f - fo) <= 1e-5 * abs(fo), w.name
+        h, ho = p.history(), np.array(o.state.history)
+        assert np.max(np.abs(h - ho) / np.maximum(np.abs(ho), 1e-2)) < 1e-3, w.name
+    for p in P:
+        p.close()
+
+
 def test_batch_respects_each_max_iters_and_mixes_with_plain_steps():
     bca = _bca()
     a = datagen.batched_instance(8, 800, 64, dtype="f64", max_iters=5)
@@ -130,8 +169,14 @@ def test_batch_autotune_keeps_state_and_results():
         assert t in (1, 2, 4, 8) and i in (64, 256, 1024)
     bca.batch_step(P, 3)
     bca.batch_step(Q, 3)
-    for p, q in zip(P, Q):
+    for w, p, q in zip(ws, P, Q):
         assert rel(p.get_vector(bca.VEC_Z), q.get_vector(bca.VEC_Z)) < 1e-5
+        # the autotuned shapes against the oracle
+        o = oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
+                           w.gamma, w.rho_c, w.rho_b, w.rho_l)
+        o.iterate(6, w.inner_iters)
+        z, oz = p.get_vector(bca.VEC_Z), o.state.z
+        assert rel(z, oz) < 1e-5 and float(np.max(np.abs(z - oz))) <= 1e-5 * float(np.max(np.abs(oz))), w.name
     for x in P + Q:
         x.close()
 

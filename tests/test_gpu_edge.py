@@ -9,6 +9,7 @@ import pytest
 import datagen
 import oracle
 from datagen import Workload
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -42,18 +43,13 @@ def run_oracle(w, iters):
     return o
 
 
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
 def check(w, iters, tol):
     g = run_gpu(w, iters)
     o = run_oracle(w, iters)
     if o.topk_margin() > 1e-6:
         assert np.array_equal(g["support"], o.support())
     assert rel(g["z"], o.state.z) < tol
-    assert rel(g["coef"], o.coef()) < tol
+    assert_coef_close(g["coef"], o.coef(), tol)
     ho = np.array(o.state.history)
     assert np.max(np.abs(g["hist"] - ho) / np.maximum(np.abs(ho), 1e-3)) < 1e3 * tol
     return g, o

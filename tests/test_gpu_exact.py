@@ -9,6 +9,7 @@ import pytest
 
 import datagen
 import oracle
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -32,11 +33,6 @@ def make(w):
 def make_oracle(w):
     return oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
                           w.gamma, w.rho_c, w.rho_b, w.rho_l, exact_x=True)
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def test_exact_inverse_and_state_match_oracle_f64():
@@ -67,7 +63,7 @@ def test_exact_inverse_and_state_match_oracle_f64():
     o.iterate(w.max_iters - 3, w.inner_iters)
     assert o.topk_margin() > 1e-6
     assert np.array_equal(P.support(), o.support())
-    assert rel(P.coef(), o.coef()) < 1e-11
+    assert_coef_close(P.coef(), o.coef(), 1e-11)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= 1e-11 * abs(fo)
     P.close()
@@ -82,7 +78,7 @@ def test_exact_f32_parity():
     o.iterate(w.max_iters, w.inner_iters)
     assert o.topk_margin() > 1e-4
     assert np.array_equal(P.support(), o.support())
-    assert rel(P.coef(), o.coef()) < 1e-5
+    assert_coef_close(P.coef(), o.coef(), 1e-5)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= 1e-5 * abs(fo)
     P.close()
@@ -97,4 +93,30 @@ def test_exact_x_parameter_checks():
     P = make(w)
     with pytest.raises(bca.BcaError):
         bca.batch_solve([P])
+    P.close()
+
+
+def test_exact_nontemporal_tile_path_matches_oracle():
+    """With more than 1 GB of H_i^-1 tiles the symmetric product reads them with
+    nontemporal loads (the path the precision-sized exact runs take): 2 partitions of
+    n = 11,600 (182 tiles per side, 2 x 16,653 stored 64 x 64 FP64 tiles = 1.09 GB),
+    FP64 data with unit-norm columns (cond(H_i) about 100, so the explicitly inverted
+    H_i^-1 is accurate to FP64 level), state against the oracle's exact mode at 1e-11
+    over three outer iterations."""
+    bca = _bca()
+    w = datagen.linear_workload(74, N=2, m_per=[300, 277], n=11600, kappa=40, k_true=40,
+                                noise=0.05, n_blocks=1, dtype="f64", normalize=True, max_iters=3)
+    tiles = 2 * (182 * 183 // 2) * 64 * 64 * 8
+    assert tiles > (1 << 30)
+    P = make(w)
+    o = make_oracle(w)
+    for _ in range(3):
+        P.step(1)
+        o.iterate(1, w.inner_iters)
+        for i in range(w.N):
+            assert rel(P.get_vector(bca.VEC_X, i), o.state.x[i]) < 1e-11
+        assert rel(P.get_vector(bca.VEC_Z), o.state.z) < 1e-11
+        pr, dr, br, it = P.residuals()
+        opr, odr, obr = o.state.history[-1]
+        assert abs(pr - opr) <= 1e-10 * max(1, opr) and abs(dr - odr) <= 1e-10 * max(1, odr)
     P.close()

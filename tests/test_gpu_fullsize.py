@@ -12,13 +12,9 @@ import pytest
 
 import datagen
 import oracle
+from parity import rel
 
 pytestmark = pytest.mark.gpu
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def test_config1_full_size_sampled_parity():

@@ -10,6 +10,7 @@ import pytest
 
 import datagen
 import oracle
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -45,11 +46,6 @@ def make_gpu(w, dtype=None, device_data=False):
 def make_oracle(w):
     return oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
                           w.gamma, w.rho_c, w.rho_b, w.rho_l)
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 # ------------------------------------------------------------------ setup: Gram, Cholesky, inverse
@@ -139,7 +135,7 @@ def test_config0_full_run_parity():
     o.iterate(w.max_iters, w.inner_iters)
     assert o.topk_margin() > 1e-6
     assert np.array_equal(P.support(), o.support())
-    assert rel(P.coef(), o.coef()) < 1e-12
+    assert_coef_close(P.coef(), o.coef(), 1e-12)
     f = P.objective()
     fo = o.objective(o.coef())
     assert abs(f - fo) <= 1e-12 * abs(fo)
@@ -175,7 +171,7 @@ def test_logistic_f32_parity_small():
     margin = o.topk_margin()
     assert margin > 1e-4, margin
     assert np.array_equal(P.support(), o.support())
-    assert rel(P.coef(), o.coef()) < 1e-5
+    assert_coef_close(P.coef(), o.coef(), 1e-5)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= 1e-5 * abs(fo)
     P.close()
@@ -195,7 +191,7 @@ def test_table1_recipe_dense_support_parity():
     assert o.topk_margin() > 1e-4
     assert np.array_equal(P.support(), o.support())
     assert np.array_equal(P.support(), np.nonzero(w.x_true)[0])
-    assert rel(P.coef(), o.coef()) < 1e-5
+    assert_coef_close(P.coef(), o.coef(), 1e-5)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= 1e-5 * abs(fo)
     P.close()
@@ -236,6 +232,32 @@ def test_bitwise_determinism_and_checkpoint_resume():
     assert np.array_equal(C.history(), A.history())
     for P in (A, B, C):
         P.close()
+
+
+def test_set_state_rejects_inconsistent_blobs():
+    """The state blob's iteration count indexes the residual history on the device:
+    a negative count, a count that disagrees with the stored scalar copy, and
+    non-finite scalars are refused (BCA_E_INVALID) before anything is uploaded."""
+    import struct
+    bca = _bca()
+    w = datagen.linear_workload(52, N=2, m_per=[120, 100], n=40, kappa=4, k_true=4, noise=0.05,
+                                n_blocks=2, dtype="f64", max_iters=6)
+    P = make_gpu(w)
+    P.step(2)
+    blob = bytearray(P.get_state())
+    # header: magic u64, n C N kappa i32, m_total i64, iter hist_cap i32, scal[8] f64
+    assert struct.unpack_from("<i", blob, 32)[0] == 2 and struct.unpack_from("<d", blob, 80)[0] == 2.0
+    bad = []
+    b1 = bytearray(blob); struct.pack_into("<i", b1, 32, -1); struct.pack_into("<d", b1, 80, -1.0)
+    b2 = bytearray(blob); struct.pack_into("<d", b2, 80, 5.0)
+    b3 = bytearray(blob); struct.pack_into("<d", b3, 40, float("nan"))
+    for b in (b1, b2, b3):
+        with pytest.raises(bca.BcaError) as e:
+            P.set_state(bytes(b))
+        assert e.value.code == -1
+    P.set_state(bytes(blob))              # the untouched blob is still accepted
+    assert P.residuals()[3] == 2
+    P.close()
 
 
 def test_error_paths():
@@ -299,7 +321,7 @@ def test_softmax_parity(dtype, C, tol):
     o.iterate(w.max_iters - 1, w.inner_iters)
     assert o.topk_margin() > 10 * tol
     assert np.array_equal(P.support(), o.support())
-    assert rel(P.coef(), o.coef()) < tol
+    assert_coef_close(P.coef(), o.coef(), tol)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= tol * abs(fo)
     h, ho = P.history(), np.array(o.state.history)

@@ -15,6 +15,7 @@ import pytest
 
 import datagen
 import oracle
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -35,10 +36,6 @@ def make(w, dtype):
     return P
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
-
-
 def test_bf16_form_against_both_references():
     kw = dict(N=3, m_per=[800, 750, 777], n=602, kappa=12, k_true=12, noise=0.05, n_blocks=4,
               normalize=True, max_iters=25)
@@ -54,13 +51,13 @@ def test_bf16_form_against_both_references():
     ob.iterate(wb.max_iters, wb.inner_iters)
     assert ob.topk_margin() > 1e-4
     assert np.array_equal(Pb.support(), ob.support())
-    assert rel(Pb.coef(), ob.coef()) < 1e-5
+    assert_coef_close(Pb.coef(), ob.coef(), 1e-5)
     assert abs(Pb.objective() - ob.objective(ob.coef())) <= 1e-5 * abs(ob.objective(ob.coef()))
     # (ii) oracle on the canonical FP32 data; FP32 form matches it to 1e-5
     o32 = oracle.BiCADMM([datagen.widen(a) for a in w32.A], w32.b, w32.loss, w32.n_blocks,
                          w32.kappa, w32.gamma, w32.rho_c, w32.rho_b, w32.rho_l)
     o32.iterate(w32.max_iters, w32.inner_iters)
-    assert rel(P32.coef(), o32.coef()) < 1e-5
+    assert_coef_close(P32.coef(), o32.coef(), 1e-5)
     cond = 0.0
     shift = 1.0 / (w32.N * w32.gamma) + w32.rho_c
     for A in w32.A:

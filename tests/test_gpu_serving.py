@@ -1,7 +1,7 @@
 """Serving form: continuous batching of sparse-fit requests.
 
 Checks: every served result matches the same request solved alone with the
-one-problem path (FP64 1e-12, FP32 1e-5); a request's result is bitwise the same
+one-problem path and the FP64 oracle (FP64 1e-12, FP32 1e-5); a request's result is bitwise the same
 alone on a server and in a mix; admission by HBM budget, slot limit and
 cancellation behave as documented.
 """
@@ -11,6 +11,8 @@ import numpy as np
 import pytest
 
 import datagen
+import oracle
+from parity import assert_coef_close
 
 pytestmark = pytest.mark.gpu
 
@@ -68,6 +70,7 @@ def test_served_results_match_solo(dtype, tol):
     tickets = [submit(S, w) for w in ws]
     st = wait_all(S, tickets)
     assert all(s == bca.REQ_DONE for s in st), st
+    checked = 0
     for w, t in zip(ws, tickets):
         idx, x, f, lat = S.fetch(t)
         sidx, sx, sf = solo(w)
@@ -76,6 +79,17 @@ def test_served_results_match_solo(dtype, tol):
         nb = np.linalg.norm(sx)
         assert np.linalg.norm(x - sx) <= tol * max(nb, 1e-30), w.name
         assert abs(f - sf) <= tol * abs(sf), w.name
+        o = oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
+                           w.gamma, w.rho_c, w.rho_b, w.rho_l, n_classes=w.n_classes)
+        o.iterate(w.max_iters, w.inner_iters)
+        zr = np.abs(o.state.z) if w.n_classes == 1 else np.linalg.norm(o.state.z, axis=1)
+        if o.topk_margin() > 1e3 * tol * float(np.max(zr)):
+            assert np.array_equal(idx, o.support()), w.name
+            assert_coef_close(x, o.coef().ravel(), tol, w.name)
+            fo = o.objective(o.coef())
+            assert abs(f - fo) <= tol * abs(fo), w.name
+            checked += 1
+    assert checked >= 4, checked
     S.close()
 
 

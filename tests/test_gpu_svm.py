@@ -11,6 +11,7 @@ import pytest
 
 import datagen
 import oracle
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -36,11 +37,6 @@ def make_oracle(w):
                           w.gamma, w.rho_c, w.rho_b, w.rho_l)
 
 
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
 def test_svm_f64_state_matches_each_outer_iteration():
     """Uneven partitions (401, 377, 350 rows) and blocks (75, 75 of n = 150)."""
     bca = _bca()
@@ -62,7 +58,7 @@ def test_svm_f64_state_matches_each_outer_iteration():
     assert o.topk_margin() > 1e-6
     assert np.array_equal(P.support(), o.support())
     assert np.array_equal(P.support(), np.nonzero(w.x_true)[0])
-    assert rel(P.coef(), o.coef()) < 1e-11
+    assert_coef_close(P.coef(), o.coef(), 1e-11)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= 1e-11 * abs(fo)
     P.close()
@@ -78,7 +74,7 @@ def test_svm_f32_parity():
     o.iterate(w.max_iters, w.inner_iters)
     assert o.topk_margin() > 1e-4
     assert np.array_equal(P.support(), o.support())
-    assert rel(P.coef(), o.coef()) < 1e-5
+    assert_coef_close(P.coef(), o.coef(), 1e-5)
     f, fo = P.objective(), o.objective(o.coef())
     assert abs(f - fo) <= 1e-5 * abs(fo)
     P.close()

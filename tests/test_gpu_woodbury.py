@@ -12,6 +12,7 @@ import pytest
 
 import datagen
 import oracle
+from parity import assert_coef_close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -39,11 +40,6 @@ def make_oracle(w):
                           w.gamma, w.rho_c, w.rho_b, w.rho_l)
 
 
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
-
-
 def _final_matches(P, o, tol, dtype):
     """z to tol; support and x_hat whenever the oracle's top-kappa margin is
     wider than the FP64-level error (else the selection is a tie).  The objective
@@ -53,7 +49,7 @@ def _final_matches(P, o, tol, dtype):
     assert rel(P.get_vector(bca.VEC_Z), o.state.z) < tol
     if o.topk_margin() > 1e-8:
         assert np.array_equal(P.support(), o.support())
-        assert rel(P.coef(), o.coef()) < tol
+        assert_coef_close(P.coef(), o.coef(), tol)
         f, fo = P.objective(), o.objective(o.coef())
         assert abs(f - fo) <= (tol if dtype == "f64" else 1e-5) * abs(fo)
 

@@ -239,6 +239,23 @@ int bca_batch_step(bca_problem* probs, int32_t count, int32_t outer_iters, void*
 /* Run every problem to its own max_iters. */
 int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream);
 
+/* bca_batch_step without device allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, kernels and results (bit for bit) as
+ * bca_batch_step.  The launch's descriptors, item lists and phase counters live
+ * in a fixed scratch array of 16 MiB in the library's device code (one copy per
+ * GPU, held until the process ends); every problem must already hold its batched
+ * partial sums, which bca_finalize allocates for every problem within the
+ * batched form's limits (bca_batch_set_shape and bca_batch_autotune resize them).
+ * Calls in one process are serialised, since they share the scratch array; the
+ * array keeps the last call's contents, and what must start at zero is cleared
+ * by each call.  Synchronises hip_stream.
+ * Errors: as bca_batch_step; BCA_E_INVALID also when the batch needs more than
+ * the 16 MiB of scratch (too many problems or items, or too many outer
+ * iterations for the phase counters); BCA_E_STATE when a problem lacks its
+ * batched partial sums. */
+int bca_batch_step_noalloc(bca_problem* probs, int32_t count, int32_t outer_iters, void* hip_stream);
+
 /* Tile-shape autotuner of the batched streaming pass: groups the problems by
  * (storage type, row length, rows per partition), times every candidate shape
  * (rows per wavefront tile 1/2/4, and 8 for rows of at most 64 16-byte chunks,

@@ -32,7 +32,7 @@ EXPORTS = ["bca_create", "bca_set_data", "bca_finalize", "bca_step", "bca_solve"
            "bca_get_support", "bca_get_coef", "bca_get_residuals", "bca_get_history",
            "bca_get_objective", "bca_get_vector", "bca_set_vector", "bca_get_state",
            "bca_set_state", "bca_get_inverse", "bca_set_timing", "bca_get_timing", "bca_destroy",
-           "bca_last_error", "bca_topk", "bca_batch_step", "bca_batch_solve",
+           "bca_last_error", "bca_topk", "bca_batch_step", "bca_batch_step_noalloc", "bca_batch_solve",
            "bca_batch_autotune", "bca_batch_set_shape", "bca_batch_get_shape",
            "bca_server_create", "bca_server_submit", "bca_server_poll", "bca_server_fetch",
            "bca_server_cancel", "bca_server_stats", "bca_server_destroy"]
@@ -85,6 +85,7 @@ def _load():
         "bca_destroy": [P],
         "bca_topk": [P, i32, i64, i32, P, P],
         "bca_batch_step": [P, i32, i32, P],
+        "bca_batch_step_noalloc": [P, i32, i32, P],
         "bca_batch_solve": [P, i32, P],
         "bca_batch_autotune": [P, i32, P],
         "bca_batch_set_shape": [P, i32, i32],
@@ -338,6 +339,12 @@ def batch_step(problems, outer_iters: int, stream=None):
     """Advance every problem by up to outer_iters outer iterations in one persistent launch."""
     st = _current_stream() if stream is None else ctypes.c_void_p(stream)
     _check(_lib.bca_batch_step(_handles(problems), len(problems), outer_iters, st))
+
+
+def batch_step_noalloc(problems, outer_iters: int, stream=None):
+    """batch_step without device allocation (the library's fixed 16 MiB scratch)."""
+    st = _current_stream() if stream is None else ctypes.c_void_p(stream)
+    _check(_lib.bca_batch_step_noalloc(_handles(problems), len(problems), outer_iters, st))
 
 
 def batch_solve(problems, stream=None):

@@ -458,6 +458,17 @@ int batch_grid_size() {
   return per * cus;
 }
 
+__global__ void zero_u32_kernel(unsigned int* p, int count) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) p[k] = 0u;
+}
+
+hipError_t launch_zero_u32(unsigned int* p, int count, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s) {
   BatchArgs arg = a;
   void* params[] = {&arg};

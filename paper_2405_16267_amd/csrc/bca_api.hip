@@ -148,6 +148,9 @@ void dfree(bca_problem P, void* p) {
 
 int xs_is_f64(bca_problem P) { return P->dtype == BCA_F64 ? 1 : 0; }
 
+bool batch_eligible(bca_problem P);
+int batch_ensure_partials(bca_problem P);
+
 // Host-to-device copy of a pitched block (m rows of `width` bytes, host pitch
 // spitch, device pitch dpitch).  A pitched copy straight from pageable host
 // memory moves row by row (about 0.5 GB/s measured); instead, row chunks are
@@ -818,6 +821,9 @@ int bca_finalize(bca_problem P) {
   P->need_prime = false;
   P->need_bprime = true;
   P->iter = 0;
+  // the batched form's partial sums of A^T e (problem state of that form), so that a
+  // finalized problem can enter bca_batch_step_noalloc without a device allocation
+  if (batch_eligible(P)) TRY(batch_ensure_partials(P));
   return BCA_OK;
 }
 
@@ -1176,6 +1182,13 @@ int batch_check(bca_problem P) {
   return BCA_OK;
 }
 
+// One-class FP32/FP64 problem with n_j <= 1,024 and a built tile shape for its rows
+// (the batched form's scope), tested without touching the error message.
+bool batch_eligible(bca_problem P) {
+  return P->C == 1 && !P->exact && !P->wood && P->dtype != BCA_BF16 && P->nj_max <= 1024 &&
+         P->nvec <= batch_max_nvec() && batch_shape_code(P->nvec, batch_rows_tile(P)) >= 0;
+}
+
 int batch_check_basic(bca_problem P) {
   if (!P->finalized) return fail(BCA_E_STATE, "batch problem not finalized");
   if (P->C != 1) return fail(BCA_E_INVALID, "the batched form handles one-class losses only");
@@ -1252,9 +1265,13 @@ BatchInst batch_desc(bca_problem P, int outer) {
 
 // One persistent launch: optional prime phase for problems whose partial sums
 // are stale, then `outer[i]` outer iterations of problem i.  stream_only runs
-// just the prime phase over all given problems (tile-shape timing).
+// just the prime phase over all given problems (tile-shape timing).  The
+// launch's descriptors, item lists and phase counters go to `dev` (`cap` bytes)
+// when it is given -- nothing is allocated then, and a problem whose batched
+// partial sums are missing or too small is refused -- else to the library's
+// growable buffer g_batch.
 int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, hipStream_t s,
-                 bool stream_only, float* ms) {
+                 bool stream_only, float* ms, void* dev = nullptr, size_t cap = 0) {
   std::vector<BatchInst> desc(count);
   std::vector<BatchItem> solve, stream, primei, symv, xupd;
   int outer_max = 0, inner_max = 0;
@@ -1263,7 +1280,14 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   constexpr int kSymvTiles = 8;
   for (int r = 0; r < count; ++r) {
     bca_problem P = probs[r];
-    TRY(batch_ensure_partials(P));
+    if (dev) {
+      const size_t need = (size_t)P->N * batch_items_per_part(P) * P->ld;
+      if (!P->bgpart || P->bgpart_count < need)
+        return fail(BCA_E_STATE, "batch problem %d has no batched partial sums for its tile shape "
+                    "(bca_finalize, bca_batch_set_shape and bca_batch_step allocate them)", r);
+    } else {
+      TRY(batch_ensure_partials(P));
+    }
     desc[r] = batch_desc(P, outer[r]);
     outer_max = std::max(outer_max, outer[r]);
     inner_max = std::max(inner_max, P->p.inner_iters);
@@ -1321,14 +1345,22 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   const size_t off_prime = off_stream + al(stream.size() * sizeof(BatchItem));
   const size_t off_cnt = off_prime + al(primei.size() * sizeof(BatchItem));
   const size_t total = off_cnt + al((size_t)std::max(phases, 1) * sizeof(unsigned int));
-  if (g_batch.cap < total) {
-    if (g_batch.buf) (void)hipFree(g_batch.buf);
-    g_batch.buf = nullptr;
-    g_batch.cap = 0;
-    HIP_TRY(hipMalloc(&g_batch.buf, total));
-    g_batch.cap = total;
+  char* base = nullptr;
+  if (dev) {
+    if (total > cap)
+      return fail(BCA_E_INVALID, "batch needs %zu bytes of launch scratch (descriptors, item lists, "
+                  "phase counters), above the %zu bytes of the no-allocation form", total, cap);
+    base = reinterpret_cast<char*>(dev);
+  } else {
+    if (g_batch.cap < total) {
+      if (g_batch.buf) (void)hipFree(g_batch.buf);
+      g_batch.buf = nullptr;
+      g_batch.cap = 0;
+      HIP_TRY(hipMalloc(&g_batch.buf, total));
+      g_batch.cap = total;
+    }
+    base = reinterpret_cast<char*>(g_batch.buf);
   }
-  char* base = reinterpret_cast<char*>(g_batch.buf);
   HIP_TRY(hipMemcpyAsync(base + off_desc, desc.data(), desc.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s));
   if (!solve.empty())
     HIP_TRY(hipMemcpyAsync(base + off_solve, solve.data(), solve.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
@@ -1340,7 +1372,8 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     HIP_TRY(hipMemcpyAsync(base + off_stream, stream.data(), stream.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   if (!primei.empty())
     HIP_TRY(hipMemcpyAsync(base + off_prime, primei.data(), primei.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(base + off_cnt, 0, (size_t)std::max(phases, 1) * sizeof(unsigned int), s));
+  // phase counters start at zero (a fill kernel rather than a memset node)
+  HIP_TRY(launch_zero_u32(reinterpret_cast<unsigned int*>(base + off_cnt), std::max(phases, 1), s));
   BatchArgs a{};
   a.inst = reinterpret_cast<const BatchInst*>(base + off_desc);
   a.count = count;
@@ -1408,6 +1441,44 @@ int bca_batch_step(bca_problem* probs, int32_t count, int32_t outer_iters, void*
   return BCA_OK;
 }
 
+// Scratch of bca_batch_step_noalloc: the descriptors, item lists and phase
+// counters of one batched launch.  Every GPU the library runs on holds its own
+// copy until the process ends; host code never passes `scratch` itself to a
+// kernel (its host-side name is not a device address) but the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kBatchScratchBytes = 16u << 20;
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;              // also serialises calls: they share the scratch
+void* g_scratch_dev[64] = {nullptr};  // per-device address of `scratch`
+}  // namespace
+
+int bca_batch_step_noalloc(bca_problem* probs, int32_t count, int32_t outer_iters, void* hip_stream) {
+  if (!probs || count < 1) return fail(BCA_E_INVALID, "empty batch");
+  if (outer_iters < 0) return fail(BCA_E_INVALID, "negative iteration count");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(BCA_E_DEVICE, "device index %d out of range", dev);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BCA_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  std::vector<int> outer(count);
+  for (int r = 0; r < count; ++r) {
+    TRY(batch_check(probs[r]));
+    outer[r] = std::max(0, std::min(outer_iters, probs[r]->p.max_iters - probs[r]->iter));
+  }
+  TRY(batch_launch(probs, count, outer, reinterpret_cast<hipStream_t>(hip_stream), false, nullptr,
+                   g_scratch_dev[dev], kBatchScratchBytes));
+  for (int r = 0; r < count; ++r) TRY(check_status(probs[r], "batch"));
+  return BCA_OK;
+}
+
 int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream) {
   if (!probs || count < 1) return fail(BCA_E_INVALID, "empty batch");
   int32_t most = 0;
@@ -1428,6 +1499,7 @@ int bca_batch_set_shape(bca_problem P, int32_t rows_per_tile, int32_t rows_per_i
   P->b_rows_tile = rows_per_tile;
   P->b_rows_item = rows_per_item;
   P->need_bprime = true;
+  if (P->finalized && batch_eligible(P)) TRY(batch_ensure_partials(P));
   return BCA_OK;
 }
 
@@ -1493,6 +1565,7 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
       P->b_rows_tile = bt;
       P->b_rows_item = bi;
       P->need_bprime = true;
+      TRY(batch_ensure_partials(P));
     }
   }
   return BCA_OK;

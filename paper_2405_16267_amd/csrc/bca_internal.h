@@ -369,6 +369,7 @@ struct BatchArgs {
   int stream_only;                 // 1: run only the prime phase (tile-shape timing)
 };
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, int count, hipStream_t s);   // p[0..count) = 0
 int batch_grid_size();            // co-resident workgroups of the batched kernel
 int batch_shape_code(int nvec, int R);  // -1 if the (chunks per lane, rows per tile) pair is not built
 int batch_max_nvec();

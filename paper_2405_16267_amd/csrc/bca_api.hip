@@ -571,7 +571,9 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   };
   {
     void* a = nullptr;
-    hipError_t e = hipMalloc(&a, (size_t)P->m_total * P->ld * es);
+    // kATailBytes past the last row: whole 16-byte pieces that straddle a block's last
+    // column may be fetched by the BF16 Gram's LDS DMA
+    hipError_t e = hipMalloc(&a, (size_t)P->m_total * P->ld * es + kATailBytes);
     if (e != hipSuccess) chk(fail(BCA_E_OOM, "hipMalloc(A) failed: %s", hipGetErrorString(e)));
     else {
       P->allocs.push_back(a);
@@ -653,7 +655,7 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     if (e == hipSuccess) e = cp(P->d_wkmat_off, P->wkmat_off.data(), P->wkmat_off.size() * sizeof(int64_t));
     if (e == hipSuccess) e = cp(P->d_wcol_off, P->wcol_off.data(), P->wcol_off.size() * sizeof(int32_t));
   }
-  if (e == hipSuccess) e = hipMemsetAsync(P->A, 0, (size_t)P->m_total * P->ld * es, s);
+  if (e == hipSuccess) e = hipMemsetAsync(P->A, 0, (size_t)P->m_total * P->ld * es + kATailBytes, s);
   if (e == hipSuccess) e = hipMemsetAsync(P->status, 0, 4 * sizeof(int), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {

@@ -173,6 +173,8 @@ struct GramArgs {
   double rho_l, shift;     // K = rho_l G + shift I
 };
 hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s);
+// Zero bytes allocated past the last row of A (reads of whole 16-byte pieces there).
+constexpr size_t kATailBytes = 256;
 
 // Tiled inverse P_ij = K_ij^-1 (FP64), the operator of the x_ij-step.  Block
 // (i, j) holds the 64 x 64 tiles (I, J), I >= J, of the lower block triangle of

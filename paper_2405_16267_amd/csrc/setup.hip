@@ -377,18 +377,171 @@ __global__ __launch_bounds__(256) void gram128_kernel(GramArgs a) {
       }
 }
 
+// BF16 Gram with 256 x 256 output tiles, fed by LDS DMA.  8 wavefronts, each
+// 128 x 64 outputs (an 8 x 4 grid of 16 x 16 tiles of v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation).  The two 256-column panels of the tile stream through LDS in
+// 32-row stages, four stages deep: global_load_lds_dwordx4 writes each panel row
+// into LDS as it sits in HBM (no registers, so three stages stay in flight while
+// the MFMAs run on the fourth), and ds_read_b64_tr_b16 reads the MFMA operands --
+// 8 consecutive rows of one column per lane -- transposed out of that row-major
+// layout.  One barrier per stage.
+//
+// LDS layout of a stage: panel P (0 = I, 1 = J), row pair p = r / 2: 1 KB, lanes
+// 0-31 of a DMA instruction fill row 2p, lanes 32-63 row 2p + 1.  Within a row the
+// 16-byte pieces (8 columns) are XOR-swizzled by 4 (p & 1) + 2 (r & 1), so the four
+// consecutive rows a group of 16 lanes reads transposed land in four different
+// 32-byte slots of the 128-byte LDS bank period.
+//
+// Block starts that are not 16-byte aligned: each panel starts delta = c0 mod 8
+// columns before its tile (delta columns of the previous block, or of this one),
+// so every DMA source is a whole aligned piece; outputs whose shifted index falls
+// outside [0, n_j) are dropped.  Pieces past the block's last column read a zero
+// vector; a piece that straddles it reads up to 7 columns beyond (harmless: they
+// only meet outputs that are dropped; A carries a zero tail for the last row).
+namespace gdma {
+constexpr int TILE = 256;
+constexpr int KB = 32;                       // rows per stage
+constexpr int STAGES = 4;
+constexpr int STAGE_BYTES = 2 * KB * 512;    // two panels x KB rows x 512 bytes
+constexpr int DMA_PER_WAVE = KB / 8;         // 16-byte DMA instructions per wavefront and stage
+__device__ __forceinline__ int swz(int p, int h) { return 4 * (p & 1) + 2 * h; }
+// byte offset in a stage of panel P, stage row r, panel column c (c % 4 == 0)
+__device__ __forceinline__ int off(int P, int r, int c) {
+  const int p = r >> 1, h = r & 1;
+  return P * (KB * 512) + p * 1024 + 16 * (32 * h + ((c >> 3) ^ swz(p, h))) + 2 * (c & 7);
+}
+// s_waitcnt with vmcnt <= n (n < 64), expcnt and lgkmcnt unconstrained
+constexpr int vmcnt(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4) | (15 << 8); }
+}  // namespace gdma
+
+__device__ const uint32_t kGramZero[4] = {0u, 0u, 0u, 0u};
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+#define BCA_LDS __attribute__((address_space(3)))
+
+__global__ __launch_bounds__(512) void gram_dma_bf16_kernel(GramArgs a) {
+  using namespace gdma;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[STAGES * STAGE_BYTES];
+
+  const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bid = lin / gridDim.x;
+  const int part = bid / a.M, blk = bid - part * a.M;
+  const int c0 = a.col_off[blk];
+  const int nj = a.col_off[blk + 1] - c0;
+  const int delta = c0 & 7;
+  const int T_ = (nj + delta + TILE - 1) / TILE;
+  int ti, tj;
+  tri_tile(lin - bid * gridDim.x, &ti, &tj);
+  if (ti >= T_) return;
+  const int64_t r0 = a.row_off[part];
+  const int64_t m = a.row_off[part + 1] - r0;
+  const uint16_t* Ab = reinterpret_cast<const uint16_t*>(a.A) + r0 * a.ld + (c0 - delta);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wv >> 2, wc = wv & 3;
+  const int64_t nch = (m + KB - 1) / KB;
+
+  // stage ch: DMA instruction q = wv + 8 i (i < DMA_PER_WAVE) fills row pair q % 16 of
+  // panel q / 16; lane l loads piece (l & 31) ^ swz of row 2p + l / 32
+  auto issue = [&](int64_t ch) {
+    unsigned char* st = smem + (int)(ch % STAGES) * STAGE_BYTES;
+#pragma unroll
+    for (int i = 0; i < DMA_PER_WAVE; ++i) {
+      const int q = wv + 8 * i;
+      const int P = q / (KB / 2), p = q % (KB / 2), h = lane >> 5;
+      const int pc = (lane & 31) ^ swz(p, h);
+      const int64_t row = ch * KB + 2 * p + h;
+      const int col = (P ? tj : ti) * TILE + 8 * pc;    // shifted column of the piece
+      const void* src = (row < m && col - delta < nj) ? (const void*)(Ab + row * a.ld + col)
+                                                       : (const void*)kGramZero;
+      const uint32_t dst = __builtin_amdgcn_readfirstlane(
+          (uint32_t)(uintptr_t)(BCA_LDS void*)(st + P * (KB * 512) + p * 1024));
+      // written out: the builtin form makes the compiler wait for all DMA before
+      // every LDS read; this kernel waits for its own stages explicitly
+      asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(dst)
+                   : "memory", "m0");
+    }
+  };
+
+  floatx4 acc[8][4];
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // a wavefront of a diagonal tile whose columns all lie above its rows has no output
+  const bool idle = ti == tj && wc * 64 >= (wr + 1) * 128;
+  const int s16 = lane & 15, g = lane >> 4;
+  const int rA = 8 * g + (s16 >> 2);    // stage row of this lane's first transposed read
+  const int cq = 4 * (s16 & 3);
+
+  for (int d = 0; d < STAGES - 1; ++d)
+    if (d < nch) issue(d);
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    // this wavefront's DMA of stage ch is complete once at most the instructions of
+    // the stages issued after it are outstanding
+    const int64_t newer = nch - 1 - ch;
+    if (newer >= 2) __builtin_amdgcn_s_waitcnt(vmcnt(2 * DMA_PER_WAVE));
+    else if (newer == 1) __builtin_amdgcn_s_waitcnt(vmcnt(DMA_PER_WAVE));
+    else __builtin_amdgcn_s_waitcnt(vmcnt(0));
+    __syncthreads();   // stage ch complete for all wavefronts; stage ch - 1 fully read
+    if (ch + STAGES - 1 < nch) issue(ch + STAGES - 1);
+    if (idle) continue;
+    const unsigned char* st = smem + (int)(ch % STAGES) * STAGE_BYTES;
+    bf16x8 ob[4];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int c = wc * 64 + 16 * y + cq;
+      const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((BCA_LDS v4i16*)(st + off(1, rA, c)));
+      const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((BCA_LDS v4i16*)(st + off(1, rA + 4, c)));
+      const short t8[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      __builtin_memcpy(&ob[y], t8, 16);
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int c = wr * 128 + 16 * x + cq;
+      const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((BCA_LDS v4i16*)(st + off(0, rA, c)));
+      const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((BCA_LDS v4i16*)(st + off(0, rA + 4, c)));
+      const short t8[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      bf16x8 oa;
+      __builtin_memcpy(&oa, t8, 16);
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(oa, ob[y], acc[x][y], 0, 0, 0);
+    }
+  }
+  if (idle) return;
+  double* K = a.kbuf + a.kmat_off[bid];
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * TILE + wr * 128 + 16 * x + 4 * g + v - delta;
+        const int col = tj * TILE + wc * 64 + 16 * y + s16 - delta;
+        if (col >= 0 && row < nj && row >= col) {
+          const double gv = (double)acc[x][y][v];
+          K[(int64_t)row * nj + col] = a.rho_l * gv + (row == col ? a.shift : 0.0);
+        }
+      }
+}
+#undef BCA_LDS
+
 hipError_t launch_gram(const GramArgs& a, int dtype, hipStream_t s) {
   if (dtype == BCA_F64) {
     dim3 grid(a.tiles_max * (a.tiles_max + 1) / 2, a.N * a.M);
     hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
   }
-  const int t128 = (a.tiles_max + 1) / 2;   // tiles_max counts 64-column tiles
-  dim3 grid(t128 * (t128 + 1) / 2, a.N * a.M);
-  if (dtype == BCA_F32)
+  if (dtype == BCA_F32) {
+    const int t128 = (a.tiles_max + 1) / 2;   // tiles_max counts 64-column tiles
+    dim3 grid(t128 * (t128 + 1) / 2, a.N * a.M);
     hipLaunchKernelGGL(gram128_kernel<float>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(gram128_kernel<bf16_t>, grid, dim3(256), 0, s, a);
+  } else {
+    // tiles_max counts 64-column tiles of the widest block; panels shift by up to 7 columns
+    const int t256 = (a.tiles_max * 64 + 7 + 255) / 256;
+    dim3 grid(t256 * (t256 + 1) / 2, a.N * a.M);
+    hipLaunchKernelGGL(gram_dma_bf16_kernel, grid, dim3(512), 0, s, a);
+  }
   return hipGetLastError();
 }
 

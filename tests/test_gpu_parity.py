@@ -72,6 +72,32 @@ def test_cached_inverse_matches_ridge_matrix(dtype):
     P.close()
 
 
+@pytest.mark.parametrize("n,M,rows", [(1201, 2, [1000, 777]), (1300, 2, [1000, 777]),
+                                      (1536, 2, [1000, 777]), (700, 1, [1000, 777]),
+                                      (1203, 3, [40, 5])],
+                         ids=["odd-block-start", "4-byte-block-start", "16-byte-block-start", "one-block",
+                              "fewer-rows-than-the-pipeline"])
+def test_bf16_gram_tiles_match_ridge_matrix(n, M, rows):
+    """The BF16 Gram's 256 x 256 tiles (several tile rows and columns, ragged last
+    tiles, block starts at odd, 4-byte and 16-byte aligned columns, row counts not a
+    multiple of the 32-row stage, and partitions of fewer rows than the stages in
+    flight), through P_ij K_ij = I with K_ij formed on the host from the BF16 data
+    widened to FP64 (unit-norm columns, so FP32 accumulation keeps the products
+    within 1e-5)."""
+    w = datagen.linear_workload(22, N=2, m_per=rows, n=n, kappa=5, k_true=5, noise=0.1,
+                                n_blocks=M, dtype="bf16", normalize=True, max_iters=3)
+    P = make_gpu(w)
+    bounds = oracle.split_columns(w.n, w.n_blocks)
+    for i in range(w.N):
+        A = datagen.widen(w.A[i])
+        for j, (c0, c1) in enumerate(bounds):
+            Aj = A[:, c0:c1]
+            K = w.rho_l * Aj.T @ Aj + (1.0 / (w.N * w.gamma) + w.rho_c) * np.eye(c1 - c0)
+            E = P.inverse(i, j) @ K - np.eye(c1 - c0)
+            assert np.max(np.abs(E)) < 1e-5, (i, j, np.max(np.abs(E)))
+    P.close()
+
+
 # ------------------------------------------------------------------ top-kappa
 def test_topk_bit_exact_on_ties():
     import torch

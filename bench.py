@@ -84,12 +84,26 @@ def workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def oracle_baseline(w, max_parts=2):
-    """The FP64 oracle, as it is, on a bounded sample: the x-update (K_in inner
-    iterations of the node-level loop) of `max_parts` partitions and one global
-    step on the full-size vectors; scaled to outer iterations per second of the
-    whole problem."""
-    import numpy as np
+def host_info():
+    """Logical CPUs, CPU model and socket count of the host that runs the oracle."""
+    model, sockets = "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "sockets": max(len(sockets), 1)}
+
+
+def oracle_baseline(w, min_seconds=10.0, max_outer=10):
+    """The FP64 oracle, as it is, on the whole problem: full outer iterations (the
+    x-update of every partition, K_in inner iterations each, then the global step)
+    from the zero state, repeated until `min_seconds` of CPU work or `max_outer`
+    iterations; its one-time factorisation is not timed."""
     import datagen
     import oracle
     try:
@@ -97,29 +111,23 @@ def oracle_baseline(w, max_parts=2):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    parts = list(range(min(max_parts, w.N)))
-    A = [datagen.widen(w.A[i]) for i in parts]
-    b = [w.b[i] for i in parts]
-    o = oracle.BiCADMM(A, b, w.loss, w.n_blocks, w.kappa, w.gamma, w.rho_c, w.rho_b, w.rho_l)
+    A = [datagen.widen(a) for a in w.A]
     t0 = time.perf_counter()
-    for i in range(len(parts)):
-        o.x_update(i, w.inner_iters)
-    tx = time.perf_counter() - t0
-    # global step at full size (N partitions of n-vectors)
-    st = o.zero_state()
-    st.x = np.random.default_rng(0).standard_normal((w.N, w.n))
-    st.u = np.zeros((w.N, w.n))
-    g = oracle.BiCADMM.__new__(oracle.BiCADMM)
-    g.N, g.n, g.M, g.kappa, g.C = w.N, w.n, w.n_blocks, w.kappa, 1
-    g.rho_c, g.rho_b = w.rho_c, w.rho_b
-    t1 = time.perf_counter()
-    g.global_update(st)
-    tg = time.perf_counter() - t1
-    per_outer = tx * (w.N / len(parts)) + tg
-    return {"value": 1.0 / per_outer, "unit": "iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": "x-update (%d inner iterations) of %d of %d partitions plus one full-size "
-                      "global step, scaled to all %d partitions; %.1f s of CPU work"
-                      % (w.inner_iters, len(parts), w.N, w.N, tx + tg)}
+    o = oracle.BiCADMM(A, w.b, w.loss, w.n_blocks, w.kappa, w.gamma, w.rho_c, w.rho_b, w.rho_l,
+                       n_classes=w.n_classes)
+    setup_s = time.perf_counter() - t0
+    k = 0
+    t0 = time.perf_counter()
+    while k < max_outer and (k == 0 or time.perf_counter() - t0 < min_seconds):
+        o.iterate(1, w.inner_iters)
+        k += 1
+    el = time.perf_counter() - t0
+    out = {"value": k / el, "unit": "iter/s", "cores": int(cores), "kind": "oracle",
+           "sample": "%d full outer iterations (all %d partitions, %d inner iterations each, "
+                     "then the global step) from the zero state: %.1f s of CPU work; the "
+                     "oracle's factorisation (%.1f s) is not timed" % (k, w.N, w.inner_iters, el, setup_s)}
+    out.update(host_info())
+    return out
 
 
 def make_problem(bca, w):
@@ -206,6 +214,7 @@ def precision_bench(args):
     rows = [m] * N
     kw = dict(gamma=10.0, rho_c=1.0, rho_b=0.5, rho_l=1.0, inner_iters=5,
               max_iters=args.warmup + args.steps)
+    kw["max_iters"] += 1             # one more outer iteration, sampled by the oracle
     Pb = bca.Problem("squared", n, rows, Mb, kappa, dtype="bf16", **kw)
     P32 = bca.Problem("squared", n, rows, Mb, kappa, dtype="f32", **kw)
     t = time.perf_counter()
@@ -258,8 +267,18 @@ def precision_bench(args):
     same_support = bool(np.array_equal(Pb.support(), P32.support()))
     ev = np.linalg.eigvalsh(P32.inverse(0, 0))
     condK = float(ev[-1] / ev[0])
+    # error against the FP64 oracle, sampled: one more outer iteration of each form, and
+    # the oracle's x-update of partition 0 (five inner iterations over its full
+    # 100,000 x 10,000 data) from the GPU's state before it
+    snap = {}
+    for name, P in (("bf16", Pb), ("f32", P32)):
+        before = dict(x0=P.get_vector(bca.VEC_X, 0), u=np.array([P.get_vector(bca.VEC_U, i) for i in range(N)]),
+                      z=P.get_vector(bca.VEC_Z), om0=P.get_vector(bca.VEC_OMEGA, 0), nu0=P.get_vector(bca.VEC_NU, 0))
+        P.step(1)
+        snap[name] = (before, P.get_vector(bca.VEC_X, 0))
     Pb.close()
     P32.close()
+    oracle_err = precision_oracle_check(snap, N, m, n, Mb, kappa, supp, val)
     err = float(np.linalg.norm(xb - x32) / np.linalg.norm(x32))
     out = {"metric": "ADMM iter/s + HBM GB/s (precision form, BF16 beside FP32)",
            "value": res["bf16"]["iter_per_s"], "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
@@ -271,7 +290,96 @@ def precision_bench(args):
            "bf16": res["bf16"], "f32": res["f32"],
            "bf16_vs_f32": {"coef_rel": err, "objective_rel": abs(fb - f32) / abs(f32),
                            "same_support": same_support, "cond_K_block0": condK,
-                           "first_order_bound": 4 * condK * 2.0 ** -8}}
+                           "first_order_bound": 4 * condK * 2.0 ** -8},
+           "vs_fp64_oracle": oracle_err}
+    print(json.dumps(out), flush=True)
+
+
+def precision_oracle_check(snap, N, m, n, M, kappa, supp, val):
+    """Relative error of partition 0's x after one outer iteration, against the FP64
+    oracle's x-update (Algorithm 2, five inner iterations) from the GPU's own state:
+    BF16 against the oracle on the BF16 data widened to FP64 (arithmetic error) and on
+    the canonical FP32 data (plus quantisation); FP32 against the canonical data."""
+    import numpy as np
+    import datagen
+    import oracle
+    from oracle.bicadmm import LOSS_SQUARED
+    t = time.perf_counter()
+    (A32, Abf), b = datagen.linear_partition(2, 0, m, n, supp, val, 0.05, "f32+bf16", True)
+    out = {}
+    for ref, A in (("bf16_data", Abf), ("canonical_f32_data", A32)):
+        o = oracle.BiCADMM([datagen.widen(A)], [b], LOSS_SQUARED, M, kappa, 10.0, 1.0, 0.5, 1.0,
+                           n_partitions=N)
+        for name in ("bf16", "f32"):
+            if ref == "bf16_data" and name == "f32":
+                continue
+            before, x_after = snap[name]
+            st = o.zero_state()
+            st.x[0] = before["x0"]
+            st.u = before["u"]
+            st.z = before["z"]
+            st.omega[0] = before["om0"]
+            st.nu[0] = before["nu0"]
+            o.x_update(0, 5, st)
+            d = x_after - st.x[0]
+            out["%s_vs_oracle_on_%s" % (name, ref)] = {
+                "x_rel": float(np.linalg.norm(d) / np.linalg.norm(st.x[0])),
+                "x_max_abs_rel": float(np.max(np.abs(d)) / np.max(np.abs(st.x[0])))}
+        del o
+    out["sample"] = ("partition 0's x after the last outer iteration (Algorithm 2's five inner "
+                     "iterations over its 100,000 x 10,000 data), from the GPU's state before it")
+    log("oracle check of the precision form %.1f s" % (time.perf_counter() - t))
+    return out
+
+
+def setup_bench(args):
+    """One-time setup at the precision workload's shape (16 partitions of 100,000 x
+    10,000, 4 feature blocks of 2,500 columns): the Gram A_ij^T A_ij on MFMA and the
+    FP64 factorisation (Cholesky, W = L^-1, K^-1 = W^T W), for BF16 and FP32 storage.
+    A is drawn on the device with torch's seeded normal generator, N(0, 1/m) (the
+    Gram's speed does not depend on the values)."""
+    import math
+    import torch
+    import paper_2405_16267_amd as bca
+    N, m, n, M = 16, args.m_per or 100000, 10000, 4
+    bounds = [(n // M + (1 if j < n % M else 0)) for j in range(M)]
+    flops = N * sum(m * nj * (nj + 1) for nj in bounds)
+    res = {}
+    for dtype, peak in (("bf16", BF16_MFMA_PEAK_TFLOPS), ("f32", FP32_MFMA_PEAK_TFLOPS)):
+        P = bca.Problem("squared", n, [m] * N, M, 100, dtype=dtype, max_iters=1)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(5)
+        b = torch.zeros(m, device="cuda", dtype=torch.float64)
+        for i in range(N):
+            X = torch.randn(m, n, device="cuda", generator=gen) / math.sqrt(m)
+            if dtype == "bf16":
+                X = X.to(torch.bfloat16).view(torch.int16)
+            P.set_data(i, X, b)
+            del X
+        torch.cuda.synchronize()
+        P.set_timing(True)
+        t = time.perf_counter()
+        P.finalize()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        _, gram_ms = P.timing(bca.KC_GRAM)
+        _, fac_ms = P.timing(bca.KC_FACTOR)
+        P.close()
+        torch.cuda.empty_cache()
+        tf = flops / (gram_ms / 1e3) / 1e12
+        log("%s: Gram %.2f ms (%.1f TFLOP/s, %.3f of peak), factorisation %.2f ms" % (dtype, gram_ms, tf, tf / peak, fac_ms))
+        res[dtype] = {"gram_ms": gram_ms, "gram_tflops": tf, "gram_peak_tflops": peak,
+                      "gram_mfma_frac": tf / peak, "factor_ms": fac_ms, "setup_s": setup_s}
+    out = {"metric": "Gram TFLOP/s (MFMA, once per problem) + factorisation ms",
+           "value": res["bf16"]["gram_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": res["bf16"]["gram_ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "gram_%dx%dx%d_M%d" % (N, m, n, M), "N": N, "m_per_partition": m,
+                      "n": n, "M": M, "flops": flops},
+           "roofline": {"bound": "mfma", "kernel": "gram_dma_bf16_kernel",
+                        "achieved": res["bf16"]["gram_tflops"], "peak": BF16_MFMA_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": res["bf16"]["gram_mfma_frac"], "traffic": None},
+           "bf16": res["bf16"], "f32": res["f32"]}
     print(json.dumps(out), flush=True)
 
 
@@ -792,13 +900,15 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve", "precision",
-                                                         "paper-shapes", "paper-sweeps", "exact", "woodbury"],
+                                                         "paper-shapes", "paper-sweeps", "exact", "woodbury",
+                                                         "setup"],
                     help="plain: one problem (default); batched: many uneven problems in one "
                          "persistent launch; serve: continuous batching on a Poisson trace; precision: "
                          "BF16 beside FP32 at 16 x 100,000 x 10,000; paper-shapes: the sparse least-squares "
                          "shapes of the paper's Table 1, end to end; paper-sweeps: the paper's rho_b convergence study and its feature and sample scaling runs; exact: the exact squared-loss x-update beside "
                          "Algorithm 2 at 16 x 100,000 x 10,000 FP32; woodbury: the sample-space x-step beside the "
-                         "default one at 8 x 800 x 10,000 FP32")
+                         "default one at 8 x 800 x 10,000 FP32; setup: the Gram and factorisation at "
+                         "the precision workload's shape, BF16 and FP32")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
@@ -841,6 +951,8 @@ def main():
         return paper_sweeps_bench(args)
     if args.mode == "woodbury":
         return woodbury_bench(args)
+    if args.mode == "setup":
+        return setup_bench(args)
 
     t = time.perf_counter()
     w = workload(args.workload)
@@ -879,6 +991,8 @@ def main():
     n_gl, gl_ms = P.timing(bca.KC_GLOBAL)
     pr, dr, br, it = P.residuals()
     log("residuals after %d iterations: p_r %.3e d_r %.3e b_r %.3e" % (it, pr, dr, br))
+    zr = np.sort(np.abs(P.get_vector(bca.VEC_Z)))[::-1]
+    margin = float(zr[w.kappa - 1] - zr[w.kappa]) if w.kappa < w.n else float("inf")
 
     m_total = sum(w.rows)
     esize = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
@@ -927,6 +1041,11 @@ def main():
         "setup": {"seconds": setup_s, "gram_ms": gram_ms, "factor_ms": fac_ms,
                   "gram_tflops": gram_tflops,
                   "gram_mfma_frac": (gram_tflops / gram_peak) if gram_tflops else None},
+        "residuals": {"iter": it, "p_r": pr, "d_r": dr, "b_r": br},
+        # |z|_(kappa) - |z|_(kappa+1) of the last timed iteration: how far the support
+        # decision is from a tie (a support comparison with the oracle is only
+        # meaningful where this exceeds the FP32 error of z)
+        "topk_margin": {"value": margin, "relative": margin / float(zr[0]) if zr[0] > 0 else None},
     }
     P.close()
     if not args.no_cpu_baseline:

@@ -136,8 +136,13 @@ int bca_set_data(bca_problem p, int32_t part, const void* A, int64_t ld, const v
 
 /* Setup of Sec. 3.1's x_ij-step, once per problem: for every partition i and
  * block j the Gram matrix A_ij^T A_ij (MFMA), K_ij = rho_l A_ij^T A_ij +
- * (1/(N gamma) + rho_c) I, its FP64 Cholesky factor L_ij and the inverse factor
- * L_ij^-1 used by the triangular solves.  Resets the ADMM state to zero.
+ * (1/(N gamma) + rho_c) I, its FP64 Cholesky factor L_ij, W_ij = L_ij^-1 and the
+ * cached inverse K_ij^-1 = W_ij^T W_ij (FP64, tiled), which every x_ij-step then
+ * applies as one symmetric matrix-vector product.  With BCA_FLAG_EXACT_X the same
+ * is done once per partition for H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I; with
+ * BCA_FLAG_WOODBURY for S_ij = rho_l A_ij A_ij^T + (1/(N gamma) + rho_c) I.  Also
+ * allocates the batched form's partial sums for problems within its limits.
+ * Resets the ADMM state to zero.
  * Errors: BCA_E_STATE (a partition was never loaded), BCA_E_NONFINITE (K_ij not
  * positive definite in FP64), BCA_E_DEVICE. */
 int bca_finalize(bca_problem p);

@@ -417,7 +417,56 @@ def test_exact_x_update_is_the_limit_of_algorithm_2():
     x = np.linalg.solve(2 * S + np.eye(n) / 10.0, 2 * sum(Ai.T @ bi for Ai, bi in zip(A, b)))
     assert np.linalg.norm(o.state.z - x) / np.linalg.norm(x) < 1e-10
     with pytest.raises(ValueError):
-        oracle.BiCADMM(A, [np.sign(bi) for bi in b], LOSS_LOGISTIC, 1, 4, 10.0, 1.0, 0.5, 1.0, exact_x=True)
+        oracle.BiCADMM(A, [np.sign(bi) for bi in b], LOSS_HINGE, 1, 4, 10.0, 1.0, 0.5, 1.0, exact_x=True)
+
+
+def test_exact_logistic_x_update_is_the_unsplit_prox():
+    """Logistic exact x-update (Newton's method on the unsplit x-subproblem of Sec. 3)
+    against SciPy's trust-region Newton minimiser of the same function, from a cold
+    and a warm start, on a random consensus state."""
+    N, m, n = 3, 70, 11
+    A, b = _problem(21, N, m, n, LOSS_LOGISTIC)
+    gam, rc = 10.0, 1.3
+    o = oracle.BiCADMM(A, b, LOSS_LOGISTIC, 2, 3, gam, rc, 0.5 * rc, 1.0, exact_x=True)
+    r = _rng(22)
+    o.state.z = r.standard_normal(n)
+    o.state.u = 0.3 * r.standard_normal((N, n))
+    for i in range(N):
+        ref = _logistic_prox_unsplit(A[i], b[i], o.state.z - o.state.u[i], N, gam, rc)
+        o.state.x[i] = 0.0
+        o.x_update_exact(i)
+        assert np.linalg.norm(o.state.x[i] - ref) <= 1e-11 * np.linalg.norm(ref)
+        o.state.x[i] = ref + 0.1 * r.standard_normal(n)        # warm start off the minimiser
+        o.x_update_exact(i)
+        assert np.linalg.norm(o.state.x[i] - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_exact_logistic_x_update_is_the_limit_of_algorithm_2():
+    """Algorithm 2's inner loop (logistic loss, M = 2 feature blocks) run long enough
+    per outer iteration approaches the exact x-update (linearly: 300 inner iterations
+    are much further off than 3000); and with kappa = n the exact variant converges
+    to the L2-regularised logistic MLE, like Algorithm 2."""
+    N, m, n = 3, 50, 10
+    A, b = _problem(23, N, m, n, LOSS_LOGISTIC)
+    args = (A, b, LOSS_LOGISTIC, 2, 4, 10.0, 1.0, 0.5, 1.0)
+    oe = oracle.BiCADMM(*args, exact_x=True)
+    oa = oracle.BiCADMM(*args)
+    oa3 = oracle.BiCADMM(*args)
+    for _ in range(2):
+        oe.iterate(1, 5)
+        oa.iterate(1, 3000)
+        oa3.iterate(1, 300)
+        ne = np.linalg.norm(oe.state.x)
+        d3000 = np.linalg.norm(oa.state.x - oe.state.x)
+        assert d3000 <= 5e-9 * ne
+        assert np.linalg.norm(oa3.state.x - oe.state.x) >= 10 * d3000
+    o = oracle.BiCADMM(A, b, LOSS_LOGISTIC, 1, n, 2.0, 2.0, 1.0, 2.0, exact_x=True)
+    o.iterate(400, 5)
+    Aall, ball = np.vstack(A), np.concatenate(b)
+    f = lambda x: np.sum(np.logaddexp(0, -ball * (Aall @ x))) + x @ x / 4.0
+    gf = lambda x: Aall.T @ (-ball / (1 + np.exp(ball * (Aall @ x)))) + x / 2.0
+    res = minimize(f, np.zeros(n), jac=gf, method="BFGS", options=dict(gtol=1e-12))
+    assert np.linalg.norm(o.state.z - res.x) / np.linalg.norm(res.x) < 1e-7
 
 
 # ------------------------------------------------------------------ P8

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbca.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["bca_api.hip", "stream.hip", "stream_mc.hip", "setup.hip", "solve.hip", "global.hip",
-           "batch.hip", "server.hip", "woodbury.hip"]
+           "batch.hip", "server.hip", "woodbury.hip", "newton.hip"]
 ARCH = os.environ.get("BCA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

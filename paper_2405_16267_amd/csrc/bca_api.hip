@@ -97,6 +97,14 @@ struct bca_problem_s {
   std::vector<char> loaded;
   bool finalized = false;
   bool exact = false;        // BCA_FLAG_EXACT_X: exact x-update, one block
+  // logistic exact x-update (Newton-CG, newton.hip): N x n vectors, m_total row values,
+  // per-partition scalars, line-search partial sums, flags
+  double *nt_r = nullptr, *nt_p = nullptr, *nt_hp = nullptr, *nt_d = nullptr, *nt_g = nullptr;
+  double *nt_rowq = nullptr, *nt_rowp = nullptr, *nt_rowd = nullptr, *nt_w = nullptr;
+  double *nt_sc = nullptr, *nt_lsp = nullptr;
+  int* nt_done = nullptr;
+  int nt_lsg = 1;            // line-search workgroups per partition
+  int nt_flags_host[2 * 256];
   double* atb = nullptr;
   bool wood = false;         // BCA_FLAG_WOODBURY: sample-space x-step
   int mw = 0, Gw = 1;        // padded rows per block; row chunks of the A^T r pass
@@ -407,8 +415,122 @@ int one_outer_wood(bca_problem P) {
   return BCA_OK;
 }
 
+NewtonArgs newton_args(bca_problem P) {
+  NewtonArgs a{};
+  a.N = P->N;
+  a.n = P->n;
+  a.tmax = (P->nj_max + PT - 1) / PT;
+  a.ld = P->ld;
+  a.row_off = P->d_row_off;
+  a.b = P->b;
+  a.x = P->x;
+  a.z = P->z;
+  a.u = P->u;
+  a.r = P->nt_r;
+  a.p = P->nt_p;
+  a.hp = P->nt_hp;
+  a.d = P->nt_d;
+  a.g = P->nt_g;
+  a.rowq = P->nt_rowq;
+  a.rowp = P->nt_rowp;
+  a.rowd = P->nt_rowd;
+  a.xs = P->xs;
+  a.xs_f64 = xs_is_f64(P);
+  a.ypart = P->ypart;
+  a.sc = P->nt_sc;
+  a.lsp = P->nt_lsp;
+  a.done = P->nt_done;
+  a.rho_c = P->p.rho_c;
+  a.inv2Ng = 0.5 / (P->N * P->p.gamma);
+  // FP64 data: CG to a relative residual of 1e-12, Newton until the step is 1e-13
+  // of x; FP32 / BF16 products limit both to about 1e-7
+  const bool f64 = P->dtype == BCA_F64;
+  a.eta2 = f64 ? 1e-24 : 1e-14;
+  a.step_tol = f64 ? 1e-13 : 1e-8;
+  return a;
+}
+
+// Newton iterations and conjugate-gradient steps per outer iteration at most; the
+// loops end early once every partition has converged (flags read every few steps)
+constexpr int kNewtonMax = 12;
+constexpr int kCgMax = 100;
+constexpr int kCgCheck = 5;
+
+int newton_flags_all(bca_problem P, bool cg) {
+  HIP_TRY(hipMemcpyAsync(P->nt_flags_host, P->nt_done, 2 * P->N * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  for (int i = 0; i < P->N; ++i)
+    if (!P->nt_flags_host[2 * i] && !(cg && P->nt_flags_host[2 * i + 1])) return 0;
+  return 1;
+}
+
+// One outer iteration with the logistic exact x-update (newton.hip).
+int one_outer_newton(bca_problem P) {
+  const NewtonArgs na = newton_args(P);
+  int64_t mx = 0;
+  for (auto r : P->rows) mx = std::max(mx, r);
+  // gradient pass: q_k = a_k^T x, derivative and Hessian weight; H p passes: a_k^T p
+  StreamArgs sg = stream_args(P, 2);
+  sg.omega = P->nt_w;
+  sg.nu = P->nt_rowq;
+  sg.part_done = P->nt_done;
+  StreamArgs sh = stream_args(P, 3);
+  sh.omega = P->nt_w;
+  sh.nu = P->nt_rowp;
+  sh.part_done = P->nt_done;
+  SolveArgs rg = solve_args(P);   // r = -g = -(A^T e) + rho_c (z - u) - s x
+  rg.rho_l = -1.0;
+  rg.rhs = P->nt_r;
+  SolveArgs rh = solve_args(P);   // H p = A^T e + s p
+  rh.rho_l = 1.0;
+  rh.rho_c = 0.0;
+  rh.shift = -P->shift;
+  rh.x = P->nt_p;
+  rh.rhs = P->nt_hp;
+  SolveArgs pr = solve_args(P);   // z = P_i r
+  pr.rhs = P->nt_r;
+  TRY(launch_ok(launch_nt_reset(na, P->stream), "newton reset"));
+  for (int it = 0; it < kNewtonMax; ++it) {
+    {
+      Timer t(P, BCA_KC_STREAM);
+      TRY(launch_ok(launch_make_xs(P->x, P->xs, xs_is_f64(P), P->N, P->n, 1, P->ld, P->stream), "make_xs"));
+      TRY(launch_ok(launch_stream(sg, P->dtype, P->stream), "stream(gradient)"));
+    }
+    {
+      Timer t(P, BCA_KC_SOLVE);
+      TRY(launch_ok(launch_reduce_rhs(rg, P->stream), "gradient"));
+      TRY(launch_ok(launch_symv(pr, P->stream), "symv(P, r)"));
+      TRY(launch_ok(launch_nt_start(na, P->stream), "newton start"));
+    }
+    for (int j = 0; j < kCgMax; ++j) {
+      {
+        Timer t(P, BCA_KC_STREAM);
+        TRY(launch_ok(launch_stream(sh, P->dtype, P->stream), "stream(H p)"));
+      }
+      Timer t(P, BCA_KC_SOLVE);
+      TRY(launch_ok(launch_reduce_rhs(rh, P->stream), "H p"));
+      TRY(launch_ok(launch_nt_cg_step(na, mx, P->stream), "cg step"));
+      TRY(launch_ok(launch_symv(pr, P->stream), "symv(P, r)"));
+      TRY(launch_ok(launch_nt_beta(na, P->stream), "cg direction"));
+      if ((j + 1) % kCgCheck == 0 && newton_flags_all(P, true)) break;
+    }
+    {
+      Timer t(P, BCA_KC_SOLVE);
+      TRY(launch_ok(launch_nt_update(na, P->nt_lsg, P->stream), "newton update"));
+    }
+    if (newton_flags_all(P, false)) break;
+  }
+  {
+    Timer t(P, BCA_KC_GLOBAL);
+    TRY(launch_ok(launch_global(global_args(P), P->stream), "global"));
+  }
+  P->iter += 1;
+  return BCA_OK;
+}
+
 int one_outer(bca_problem P) {
   if (P->wood) return one_outer_wood(P);
+  if (P->exact && P->p.loss == BCA_LOSS_LOGISTIC) return one_outer_newton(P);
   const SolveArgs sa = solve_args(P);
   if (P->exact) {
     {
@@ -480,8 +602,8 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     return fail(BCA_E_INVALID, "BCA_FLAG_EXACT_X and BCA_FLAG_WOODBURY exclude each other");
   if ((p.flags & BCA_FLAG_WOODBURY) && p.loss == BCA_LOSS_SOFTMAX)
     return fail(BCA_E_INVALID, "the sample-space x-step handles one-class losses only");
-  if ((p.flags & BCA_FLAG_EXACT_X) && p.loss != BCA_LOSS_SQUARED)
-    return fail(BCA_E_INVALID, "the exact x-update needs the squared loss");
+  if ((p.flags & BCA_FLAG_EXACT_X) && p.loss != BCA_LOSS_SQUARED && p.loss != BCA_LOSS_LOGISTIC)
+    return fail(BCA_E_INVALID, "the exact x-update needs the squared or the logistic loss");
   for (int i = 0; i < p.n_partitions; ++i)
     if (p.rows[i] < 1) return fail(BCA_E_INVALID, "rows[%d] must be >= 1", i);
   {
@@ -613,6 +735,20 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
   if (rc == BCA_OK) chk(dalloc(P, &P->gpart, (size_t)P->N * P->Gp * P->ld * C));
   if (rc == BCA_OK) chk(dalloc(P, &P->kinv, (size_t)P->fac_total));
   if (rc == BCA_OK && P->exact) chk(dalloc(P, &P->atb, (size_t)P->N * P->n));
+  if (rc == BCA_OK && P->exact && p.loss == BCA_LOSS_LOGISTIC) {
+    if (P->N > 256) chk(fail(BCA_E_INVALID, "the logistic exact x-update handles at most 256 partitions"));
+    const size_t nv = (size_t)P->N * P->n;
+    int64_t mx = 0;
+    for (auto r : P->rows) mx = std::max(mx, r);
+    P->nt_lsg = (int)std::max<int64_t>(1, std::min<int64_t>(64, (mx + 2047) / 2048));
+    for (double** q : {&P->nt_r, &P->nt_p, &P->nt_hp, &P->nt_d, &P->nt_g})
+      if (rc == BCA_OK) chk(dalloc(P, q, nv));
+    for (double** q : {&P->nt_rowq, &P->nt_rowp, &P->nt_rowd, &P->nt_w})
+      if (rc == BCA_OK) chk(dalloc(P, q, (size_t)P->m_total));
+    if (rc == BCA_OK) chk(dalloc(P, &P->nt_sc, (size_t)P->N * NT_SCAL));
+    if (rc == BCA_OK) chk(dalloc(P, &P->nt_lsp, (size_t)P->N * P->nt_lsg * NT_LS));
+    if (rc == BCA_OK) chk(dalloc(P, &P->nt_done, (size_t)2 * P->N));
+  }
   if (P->wood) {
     const size_t nw = (size_t)P->N * P->M * P->mw;
     if (rc == BCA_OK) chk(dalloc(P, &P->wt, nw));
@@ -736,8 +872,10 @@ int bca_finalize(bca_problem P) {
   g.N = P->N;
   g.M = P->M;
   g.tiles_max = (P->nj_max + 63) / 64;
-  // the exact x-update factors H_i = 2 A_i^T A_i + shift I (the squared loss's Hessian)
-  g.rho_l = P->exact ? 2.0 : P->p.rho_l;
+  // the exact x-update factors H_i = 2 A_i^T A_i + shift I (the squared loss's
+  // Hessian); the logistic one A_i^T A_i / 4 + shift I, a bound of its Hessian that
+  // preconditions the Newton directions' conjugate gradients
+  g.rho_l = P->exact ? (P->p.loss == BCA_LOSS_LOGISTIC ? 0.25 : 2.0) : P->p.rho_l;
   g.shift = P->shift;
   FactorArgs f{};
   f.kbuf = kbuf;
@@ -794,7 +932,7 @@ int bca_finalize(bca_problem P) {
     if (e == hipSuccess) e = hipMemsetAsync(P->wd, 0, nw, s);
     if (e == hipSuccess) e = hipMemsetAsync(P->wr, 0, nw, s);
   }
-  if (e == hipSuccess && P->exact) {
+  if (e == hipSuccess && P->exact && P->p.loss == BCA_LOSS_SQUARED) {
     // 2 A_i^T b_i, streamed once: the re-derivation pass with omega-bar = b, nu = 0
     // and x = 0 accumulates sum_k b_k a_k, and the reduction scales it by 2
     const size_t mb = (size_t)P->m_total * sizeof(double);

@@ -131,7 +131,11 @@ struct StreamArgs {
   int64_t m_total;
   int N, Gp, nvec, n, M, C, loss;
   double inv_M, rho_l;
-  int mode;                // 0: inner iteration; 1: prime (e from stored state, no prox)
+  int mode;                // 0: inner iteration; 1: prime (e from stored state, no prox);
+                           // 2, 3: gradient and Hessian-vector passes of the logistic
+                           // exact x-update (Newton-CG, newton.hip)
+  const int* part_done;    // modes 2, 3 (or null): N x 2 flags, Newton ended / CG ended;
+                           // a partition with either set (mode 3) or the first (mode 2) is skipped
 };
 
 // Objective: per-workgroup partial loss sums of l(A_i xhat; b_i).
@@ -244,6 +248,35 @@ hipError_t launch_symv(const SolveArgs& a, hipStream_t s);
 hipError_t launch_reduce_rhs(const SolveArgs& a, hipStream_t s);
 // Exact x-update (squared loss, one block per partition): x = P (atb + rho_c (z - u)).
 hipError_t launch_solve_exact(const SolveArgs& a, hipStream_t s);
+
+// Exact x-update of the logistic loss (newton.hip): Newton's method on every
+// partition's whole x-subproblem, conjugate gradients for the Newton direction.
+constexpr int NT_LS = 17;     // line-search trial steps 2^-l (l < 16) and 0
+constexpr int NT_SCAL = 8;    // per-partition scalars
+enum { NT_RZ = 0, NT_RZ0 = 1, NT_ALPHA = 2 };
+struct NewtonArgs {
+  int N, n, tmax;
+  int64_t ld;
+  const int64_t* row_off;  // N + 1
+  const double* b;         // labels
+  double* x;               // N x n
+  const double* z;         // n
+  const double* u;         // N x n
+  double *r, *p, *hp, *d, *g;      // N x n: CG residual, direction, H p, Newton step, gradient
+  double *rowq, *rowp, *rowd;      // m_total: a_k^T x, a_k^T p, a_k^T d
+  void* xs;                // streaming copy (of p during CG)
+  int xs_f64;
+  const double* ypart;     // slots of the symmetric product with P_i
+  double* sc;              // N x NT_SCAL
+  double* lsp;             // N x line-search workgroups x NT_LS
+  int* done;               // N x 2: Newton ended, CG ended
+  double rho_c, inv2Ng, eta2, step_tol;
+};
+hipError_t launch_nt_reset(const NewtonArgs& a, hipStream_t s);
+hipError_t launch_nt_start(const NewtonArgs& a, hipStream_t s);
+hipError_t launch_nt_cg_step(const NewtonArgs& a, int64_t max_rows, hipStream_t s);
+hipError_t launch_nt_beta(const NewtonArgs& a, hipStream_t s);
+hipError_t launch_nt_update(const NewtonArgs& a, int ls_groups, hipStream_t s);
 
 struct GlobalArgs {
   double* x;               // N x n x C

@@ -42,6 +42,8 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
 
   const int part = blockIdx.x / a.Gp;
   const int wg = blockIdx.x - part * a.Gp;
+  if (a.part_done && (a.part_done[2 * part] || (a.mode == 3 && a.part_done[2 * part + 1])))
+    return;   // Newton passes: this partition's iteration (or its CG solve) has ended
   const int64_t r0 = a.row_off[part];
   const int64_t m = a.row_off[part + 1] - r0;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -133,16 +135,29 @@ __global__ __launch_bounds__(NT) void stream_kernel(StreamArgs a) {
         for (int w = 0; w < NW; ++w) sacc += red[w][r];
         const double av = sacc * a.inv_M;
         const int64_t gr = r0 + row;
-        double nu = a.nu[gr];
         if (a.mode == 0) {
+          double nu = a.nu[gr];
           const double om = prox_scalar(a.loss, av + nu, a.b[gr], a.M, a.rho_l,
                                         a.loss == BCA_LOSS_SQUARED ? 0.0 : a.omega[gr]);
           nu = nu + av - om;
           a.omega[gr] = om;
           a.nu[gr] = nu;
           e = om - av - nu;
+        } else if (a.mode == 1) {
+          e = a.omega[gr] - av - a.nu[gr];
+        } else if (a.mode == 2) {
+          // Newton gradient pass of the logistic exact x-update (one block, so av =
+          // a_k^T x): loss derivative, Hessian weight to omega, q_k to nu
+          const double b = a.b[gr];
+          const double sg = 1.0 / (1.0 + exp(b * av));   // sigmoid(-b q)
+          e = -b * sg;
+          a.omega[gr] = sg * (1.0 - sg);
+          a.nu[gr] = av;
         } else {
-          e = a.omega[gr] - av - nu;
+          // Hessian-vector pass (av = a_k^T p): weighted by the stored Hessian weight,
+          // a_k^T p to nu
+          e = a.omega[gr] * av;
+          a.nu[gr] = av;
         }
       }
       e_sh[r] = e;

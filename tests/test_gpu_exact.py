@@ -1,8 +1,10 @@
-"""Exact x-update of the squared loss (BCA_FLAG_EXACT_X) against the FP64 oracle's
-exact mode (itself pinned to Algorithm 2's inner-loop limit and the global ridge
-solution): the cached H_i^-1, the state after each outer iteration (FP64, 1e-12),
-a full FP32 run (support exact, coefficients and objective 1e-5), and the
-parameter checks.
+"""Exact x-update (BCA_FLAG_EXACT_X) against the FP64 oracle's exact mode (itself
+pinned to Algorithm 2's inner-loop limit, the global ridge solution and, for the
+logistic loss, SciPy's trust-region Newton minimiser and the regularised MLE).
+Squared loss: the cached H_i^-1, the state after each outer iteration (FP64,
+1e-12), a full FP32 run (support exact, coefficients and objective 1e-5), the
+nontemporal tile path.  Logistic loss (Newton-CG): the state per outer iteration
+and a full run in FP64 (1e-10) and FP32 (1e-5).  Parameter checks.
 """
 import numpy as np
 import pytest
@@ -87,7 +89,7 @@ def test_exact_f32_parity():
 def test_exact_x_parameter_checks():
     bca = _bca()
     with pytest.raises(bca.BcaError):
-        bca.Problem("logistic", 20, [50], 1, 3, dtype="f64", exact_x=True)
+        bca.Problem("hinge", 20, [50], 1, 3, dtype="f64", exact_x=True)
     w = datagen.linear_workload(73, N=2, m_per=[60, 55], n=20, kappa=3, k_true=3, noise=0.05,
                                 n_blocks=1, dtype="f64", max_iters=5)
     P = make(w)
@@ -119,4 +121,61 @@ def test_exact_nontemporal_tile_path_matches_oracle():
         pr, dr, br, it = P.residuals()
         opr, odr, obr = o.state.history[-1]
         assert abs(pr - opr) <= 1e-10 * max(1, opr) and abs(dr - odr) <= 1e-10 * max(1, odr)
+    P.close()
+
+
+# ------------------------------------------------------------------ logistic: Newton-CG
+def make_logistic(w):
+    bca = _bca()
+    P = bca.Problem("logistic", w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
+                    rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=w.max_iters, dtype=w.dtype, exact_x=True)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    return P
+
+
+def test_exact_logistic_state_matches_oracle_f64():
+    """Logistic exact x-update (Newton's method on each partition's whole x-subproblem,
+    conjugate gradients preconditioned with (A_i^T A_i / 4 + s I)^-1 on the GPU, exact
+    Hessian solves in the oracle) on uneven partitions, one of them with fewer rows than
+    features: x, u, z after each of the first outer iterations and the final support,
+    coefficients and objective against the oracle's exact mode, FP64 at 1e-10."""
+    bca = _bca()
+    w = datagen.logistic_workload(75, N=3, m_per=[420, 390, 150], n=230, kappa=9, k_true=9,
+                                  n_blocks=1, dtype="f64", max_iters=25)
+    P = make_logistic(w)
+    o = make_oracle(w)
+    for _ in range(3):
+        P.step(1)
+        o.iterate(1, w.inner_iters)
+        for i in range(w.N):
+            assert rel(P.get_vector(bca.VEC_X, i), o.state.x[i]) < 1e-10
+            assert rel(P.get_vector(bca.VEC_U, i), o.state.u[i]) < 1e-10
+        assert rel(P.get_vector(bca.VEC_Z), o.state.z) < 1e-10
+    P.step(w.max_iters - 3)
+    o.iterate(w.max_iters - 3, w.inner_iters)
+    assert o.topk_margin() > 1e-6
+    assert np.array_equal(P.support(), o.support())
+    assert_coef_close(P.coef(), o.coef(), 1e-10)
+    f, fo = P.objective(), o.objective(o.coef())
+    assert abs(f - fo) <= 1e-10 * abs(fo)
+    P.close()
+
+
+def test_exact_logistic_f32_parity():
+    """The same in FP32 storage on the sparse logistic recipe (AR(1) rows): support
+    exact, coefficients and objective within 1e-5 of the FP64 oracle."""
+    w = datagen.logistic_workload(76, N=4, m_per=[900, 820, 760, 700], n=300, kappa=12, k_true=12,
+                                  n_blocks=1, dtype="f32", max_iters=20)
+    P = make_logistic(w)
+    P.step(w.max_iters)
+    o = make_oracle(w)
+    o.iterate(w.max_iters, w.inner_iters)
+    assert o.topk_margin() > 1e-4
+    assert np.array_equal(P.support(), o.support())
+    assert_coef_close(P.coef(), o.coef(), 1e-5)
+    f, fo = P.objective(), o.objective(o.coef())
+    assert abs(f - fo) <= 1e-5 * abs(fo)
     P.close()

@@ -790,6 +790,66 @@ def exact_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def exact_logistic_bench(args):
+    """Exact x-update of the logistic loss (Newton-CG) beside Algorithm 2 on the
+    default workload's data (sparse logistic regression, 8 partitions of 50,000 x
+    5,000 FP32, AR(1) rows): both run the same `steps` outer iterations from the
+    zero state.  Reported: iter/s, passes over A per outer iteration (gradient and
+    Hessian-vector passes against Algorithm 2's K_in fused passes), the residuals
+    reached, and the two results' agreement."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_2405_16267_amd as bca
+    w = datagen.config1()
+    res, probs = {}, {}
+    for name, exact in (("algorithm2", False), ("exact_newton_cg", True)):
+        P = bca.Problem("logistic", w.n, w.rows, 1 if exact else w.n_blocks, w.kappa, gamma=w.gamma,
+                        rho_c=w.rho_c, rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                        max_iters=args.steps, dtype=w.dtype, exact_x=exact)
+        for i in range(w.N):
+            P.set_data(i, w.A[i], w.b[i])
+        P.set_timing(True)
+        t = time.perf_counter()
+        P.finalize()
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        _, gram_ms = P.timing(bca.KC_GRAM)
+        _, fac_ms = P.timing(bca.KC_FACTOR)
+        t0 = time.perf_counter()
+        P.step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n_st, st_ms = P.timing(bca.KC_STREAM)
+        n_so, so_ms = P.timing(bca.KC_SOLVE)
+        n_gl, gl_ms = P.timing(bca.KC_GLOBAL)
+        pr, dr, br, it = P.residuals()
+        log("%s: %.2f iter/s, %.1f streaming launches per outer iteration, p_r %.3e d_r %.3e"
+            % (name, args.steps / el, n_st / args.steps, pr, dr))
+        res[name] = {"iter_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
+                     "stream_launches_per_outer": n_st / args.steps,
+                     "kernels_ms_per_step": {"stream": st_ms / args.steps, "solve": so_ms / args.steps,
+                                             "global": gl_ms / args.steps},
+                     "setup": {"seconds": setup_s, "gram_ms": gram_ms, "factor_ms": fac_ms},
+                     "residuals": {"iter": it, "p_r": pr, "d_r": dr, "b_r": br}}
+        probs[name] = P
+    a2, ex = probs["algorithm2"], probs["exact_newton_cg"]
+    same = bool(np.array_equal(a2.support(), ex.support()))
+    diff = float(np.linalg.norm(a2.coef() - ex.coef()) / max(np.linalg.norm(ex.coef()), 1e-300))
+    for P in probs.values():
+        P.close()
+    out = {"metric": "ADMM iter/s (logistic exact x-update by Newton-CG beside Algorithm 2)",
+           "value": res["exact_newton_cg"]["iter_per_s"], "unit": "iter/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 0, "ms_per_step": res["exact_newton_cg"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "slogr_8x50000x5000_f32_exact_x", "N": w.N, "m_per_partition": w.rows[0],
+                      "n": w.n, "kappa": w.kappa, "inner_iters": w.inner_iters},
+           "exact_newton_cg": res["exact_newton_cg"], "algorithm2": res["algorithm2"],
+           "agreement_after_equal_iterations": {"same_support": same, "coef_rel_diff": diff}}
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Continuous batching on a Poisson trace versus the plain one-at-a-time method
     on the same trace.  Requests: 80% sparse-fit problems of the batched size
@@ -901,14 +961,15 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batched", "serve", "precision",
                                                          "paper-shapes", "paper-sweeps", "exact", "woodbury",
-                                                         "setup"],
+                                                         "setup", "exact-logistic"],
                     help="plain: one problem (default); batched: many uneven problems in one "
                          "persistent launch; serve: continuous batching on a Poisson trace; precision: "
                          "BF16 beside FP32 at 16 x 100,000 x 10,000; paper-shapes: the sparse least-squares "
                          "shapes of the paper's Table 1, end to end; paper-sweeps: the paper's rho_b convergence study and its feature and sample scaling runs; exact: the exact squared-loss x-update beside "
                          "Algorithm 2 at 16 x 100,000 x 10,000 FP32; woodbury: the sample-space x-step beside the "
                          "default one at 8 x 800 x 10,000 FP32; setup: the Gram and factorisation at "
-                         "the precision workload's shape, BF16 and FP32")
+                         "the precision workload's shape, BF16 and FP32; exact-logistic: the logistic "
+                         "exact x-update (Newton-CG) beside Algorithm 2 on the default workload")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
@@ -953,6 +1014,8 @@ def main():
         return woodbury_bench(args)
     if args.mode == "setup":
         return setup_bench(args)
+    if args.mode == "exact-logistic":
+        return exact_logistic_bench(args)
 
     t = time.perf_counter()
     w = workload(args.workload)

@@ -91,14 +91,21 @@ typedef struct {
   uint32_t flags;        /* BCA_FLAG_* bits, 0 for the paper's method as written */
 } bca_params;
 
-/* Variant of the x-update (Sec. 3.1).  EXACT_X, squared loss only: the x-update
- * of every partition is solved exactly, x_i = H_i^-1 (2 A_i^T b_i + rho_c (z -
- * u_i)) with H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I, i.e. the limit of
- * Algorithm 2's inner loop, instead of inner_iters warm-started inner iterations.
- * H_i^-1 is formed once at finalize (n x n per partition, FP64) and A_i^T b_i is
- * streamed once, so an outer iteration reads no A at all; n_blocks is then
- * ignored (one block of n features) and the omega-bar / nu state stays zero.
- * Not available in the batched and serving forms. */
+/* Variant of the x-update (Sec. 3.1).  EXACT_X, squared or logistic loss: the
+ * x-update of every partition is solved exactly -- the limit of Algorithm 2's
+ * inner loop -- instead of by inner_iters warm-started inner iterations; n_blocks
+ * is then ignored (one block of n features) and the omega-bar / nu state stays
+ * zero.  Squared loss: x_i = H_i^-1 (2 A_i^T b_i + rho_c (z - u_i)) with
+ * H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I; H_i^-1 is formed once at finalize
+ * (n x n per partition, FP64) and A_i^T b_i is streamed once, so an outer
+ * iteration reads no A at all.  Logistic loss: Newton's method on the whole
+ * subproblem, each direction by conjugate gradients preconditioned with the
+ * cached (A_i^T A_i / 4 + (1/(N gamma) + rho_c) I)^-1 and stopped by an inexact-
+ * Newton forcing term; every CG iteration is one pass over A (Hessian-vector
+ * product), the step length an Armijo search over stored row values; the Newton
+ * iteration stops once the step is below 1e-13 (FP64 data) or 1e-8 (FP32, BF16)
+ * of max|x_i|, or after 12 Newton iterations of at most 100 CG iterations each;
+ * needs N <= 256.  Not available in the batched and serving forms. */
 enum { BCA_FLAG_EXACT_X = 1 };
 
 /* WOODBURY, one-class losses (squared, logistic, hinge): the same iteration
@@ -139,7 +146,9 @@ int bca_set_data(bca_problem p, int32_t part, const void* A, int64_t ld, const v
  * (1/(N gamma) + rho_c) I, its FP64 Cholesky factor L_ij, W_ij = L_ij^-1 and the
  * cached inverse K_ij^-1 = W_ij^T W_ij (FP64, tiled), which every x_ij-step then
  * applies as one symmetric matrix-vector product.  With BCA_FLAG_EXACT_X the same
- * is done once per partition for H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I; with
+ * is done once per partition for H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I
+ * (squared loss) or the preconditioner A_i^T A_i / 4 + (1/(N gamma) + rho_c) I
+ * (logistic loss); with
  * BCA_FLAG_WOODBURY for S_ij = rho_l A_ij A_ij^T + (1/(N gamma) + rho_c) I.  Also
  * allocates the batched form's partial sums for problems within its limits.
  * Resets the ADMM state to zero.

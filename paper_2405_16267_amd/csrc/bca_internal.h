@@ -253,7 +253,7 @@ hipError_t launch_solve_exact(const SolveArgs& a, hipStream_t s);
 // partition's whole x-subproblem, conjugate gradients for the Newton direction.
 constexpr int NT_LS = 17;     // line-search trial steps 2^-l (l < 16) and 0
 constexpr int NT_SCAL = 8;    // per-partition scalars
-enum { NT_RZ = 0, NT_RZ0 = 1, NT_ALPHA = 2 };
+enum { NT_RZ = 0, NT_RZ0 = 1, NT_ALPHA = 2, NT_RZF = 3, NT_ETA2 = 4 };
 struct NewtonArgs {
   int N, n, tmax;
   int64_t ld;

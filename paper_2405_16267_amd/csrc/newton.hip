@@ -14,6 +14,12 @@
 // phi over the sample-space values q_k + t a_k^T d, which the passes leave in row
 // buffers, so no further pass over A is needed.
 //
+// CG stops once the preconditioned residual has fallen by the forcing factor
+// eta_k = min(1/2, sqrt(|g_k| / |g_0|)) (|.| the P_i-norm, g_0 the gradient at the
+// first Newton iteration of this x-update), floored at the working precision's
+// tolerance: loose solves while far from the minimiser, tight ones near it, the
+// inexact Newton method of Dembo, Eisenstat and Steihaug (superlinear).
+//
 // All partitions advance together; a partition whose Newton iteration (or CG)
 // has ended is skipped by every kernel (flags in `done`).  Everything here is FP64.
 #include "bca_internal.h"
@@ -64,6 +70,9 @@ __global__ __launch_bounds__(NTB) void nt_start_kernel(NewtonArgs a) {
     sc[NT_RZ] = rz;
     sc[NT_RZ0] = rz;
     sc[NT_ALPHA] = 0.0;
+    if (!(sc[NT_RZF] > 0.0)) sc[NT_RZF] = rz;   // first Newton iteration of this x-update
+    const double f = rz > 0.0 ? sqrt(rz / sc[NT_RZF]) : 0.0;   // eta_k^2 = |g_k| / |g_0|
+    sc[NT_ETA2] = fmax(a.eta2, fmin(0.25, f));
     dn[1] = !(rz > 0.0);   // g = 0: nothing to solve
   }
 }
@@ -99,7 +108,7 @@ __global__ __launch_bounds__(256) void nt_rowd_kernel(NewtonArgs a) {
   if (k < a.row_off[part + 1]) a.rowd[k] += alpha * a.rowp[k];
 }
 
-// z = P r (slots); beta = r^T z / rz; p = z + beta p; CG ends once r^T z <= eta^2 rz0
+// z = P r (slots); beta = r^T z / rz; p = z + beta p; CG ends once r^T z <= eta_k^2 rz0
 __global__ __launch_bounds__(NTB) void nt_beta_kernel(NewtonArgs a) {
   __shared__ double sh[NTB / 64];
   const int part = blockIdx.x;
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(NTB) void nt_beta_kernel(NewtonArgs a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     sc[NT_RZ] = rz;
-    if (!(rz > a.eta2 * sc[NT_RZ0])) dn[1] = 1;
+    if (!(rz > sc[NT_ETA2] * sc[NT_RZ0])) dn[1] = 1;
   }
 }
 
@@ -230,13 +239,15 @@ __global__ __launch_bounds__(NTB) void nt_update_kernel(NewtonArgs a, int ls_gro
   }
 }
 
-__global__ void nt_reset_kernel(int* done, int N) {
+// start of an x-update: flags cleared, the reference gradient norm unset
+__global__ void nt_reset_kernel(int* done, double* sc, int N) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < 2 * N) done[k] = 0;
+  if (k < N) sc[NT_SCAL * k + NT_RZF] = 0.0;
 }
 
 hipError_t launch_nt_reset(const NewtonArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(nt_reset_kernel, dim3((2 * a.N + 255) / 256), dim3(256), 0, s, a.done, a.N);
+  hipLaunchKernelGGL(nt_reset_kernel, dim3((2 * a.N + 255) / 256), dim3(256), 0, s, a.done, a.sc, a.N);
   return hipGetLastError();
 }
 

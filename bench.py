@@ -850,11 +850,23 @@ def exact_logistic_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# Offered rate of the serving trace, frozen: 1.5 x the plain method's rate on the
+# trace's first 20 requests, measured on one MI355X with the current kernels
+# (`--rate 0` measures it again and uses that instead).
+SERVE_PLAIN_RATE = 35.0
+SERVE_RATE = 1.5 * SERVE_PLAIN_RATE
+
+
 def serve_bench(args):
     """Continuous batching on a Poisson trace versus the plain one-at-a-time method
     on the same trace.  Requests: 80% sparse-fit problems of the batched size
     distribution (even: squared, odd: logistic), 20% softmax (C = 10, n = 1000,
-    m = 20,000, 30 nonzero rows); each runs `iters` outer iterations."""
+    m = 20,000, 30 nonzero rows); each runs `iters` outer iterations.  Arrivals are
+    Poisson at a frozen rate (1.5 x plain).  Reported for both methods: completions
+    per second over the whole trace and over its steady window (the releases of
+    requests R/10 .. 9R/10), latency percentiles after the first R/10 requests, and
+    the backlog (submitted, not finished) sampled through the window: a stable
+    queue keeps it flat, an overloaded one grows it."""
     import threading
     import numpy as np
     import torch
@@ -871,6 +883,8 @@ def serve_bench(args):
         else:
             ws.append(datagen.batched_instance(r, int(ms[r]), int(ns[r]), base_seed=4000,
                                                max_iters=args.iters))
+        if (r + 1) % 250 == 0:
+            log("generated %d of %d requests (%.0f s)" % (r + 1, R, time.perf_counter() - t))
     log("generated %d requests (%d softmax) in %.1f s" % (R, int(kind.sum()), time.perf_counter() - t))
 
     def plain_solve(w):
@@ -888,22 +902,41 @@ def serve_bench(args):
     for w in ws[:ncal]:
         plain_solve(w)
     plain_rate = ncal / (time.perf_counter() - t)
-    lam = 1.5 * plain_rate
+    lam = args.rate if args.rate > 0 else 1.5 * plain_rate
     gaps = -np.log(datagen.uniform_vector(4, datagen.S_ARRIVAL, R)) / lam
     release = np.cumsum(gaps)
-    log("plain %.2f solves/s; offered rate %.2f req/s" % (plain_rate, lam))
+    w0, w1 = R // 10, (9 * R) // 10
+    log("plain calibration %.2f solves/s; offered rate %.2f req/s (%s)"
+        % (plain_rate, lam, "frozen" if args.rate > 0 else "1.5 x this calibration"))
+
+    def summarise(done_at, lat, backlog):
+        """done_at: completion times from the trace start; backlog: (t, count) samples."""
+        win = release[w1] - release[w0]
+        in_win = np.sum((done_at >= release[w0]) & (done_at < release[w1]))
+        b = np.array([c for (tt, c) in backlog if release[w0] <= tt < release[w1]] or [0])
+        q = max(1, len(b) // 4)
+        return {"solves_per_s": R / float(np.max(done_at)),
+                "steady_solves_per_s": float(in_win / win),
+                "p50_s": float(np.percentile(lat[w0:], 50)), "p99_s": float(np.percentile(lat[w0:], 99)),
+                "backlog_mean": float(np.mean(b)), "backlog_max": int(np.max(b)),
+                "backlog_first_quarter": float(np.mean(b[:q])), "backlog_last_quarter": float(np.mean(b[-q:]))}
 
     # plain method on the trace: one FIFO worker
     lat_plain = np.zeros(R)
+    done_plain = np.zeros(R)
+    backlog_plain = []
     t0 = time.perf_counter()
     for r, w in enumerate(ws):
         now = time.perf_counter() - t0
         if now < release[r]:
             time.sleep(release[r] - now)
         plain_solve(w)
-        lat_plain[r] = time.perf_counter() - t0 - release[r]
-    span_plain = time.perf_counter() - t0
-    log("plain trace done in %.1f s" % span_plain)
+        done_plain[r] = time.perf_counter() - t0
+        lat_plain[r] = done_plain[r] - release[r]
+        backlog_plain.append((done_plain[r], int(np.searchsorted(release, done_plain[r])) - (r + 1)))
+        if (r + 1) % 200 == 0:
+            log("plain: %d of %d done at %.1f s (latency %.2f s)" % (r + 1, R, done_plain[r], lat_plain[r]))
+    log("plain trace done in %.1f s" % (time.perf_counter() - t0))
 
     # served on the same trace
     S = bca.Server(64 << 30, max_slots=256, round_iters=5)
@@ -922,31 +955,55 @@ def serve_bench(args):
 
     th = threading.Thread(target=submitter)
     th.start()
-    th.join()
     lat_srv = np.zeros(R)
+    done_srv = np.full(R, np.inf)
     done = np.zeros(R, dtype=bool)
+    backlog_srv = []
+    failed = 0
+    next_log = 200
     while not done.all():
+        now = time.perf_counter() - t0
         for r in range(R):
-            if not done[r] and S.poll(tickets[r]) in (bca.REQ_DONE, bca.REQ_FAILED, bca.REQ_CANCELLED):
-                lat_srv[r] = S.fetch(tickets[r])[3]
-                done[r] = True
-        time.sleep(0.002)
+            if not done[r] and tickets[r] is not None:
+                st = S.poll(tickets[r])
+                if st in (bca.REQ_DONE, bca.REQ_FAILED, bca.REQ_CANCELLED):
+                    done[r] = True
+                    done_srv[r] = now
+                    if st == bca.REQ_DONE:
+                        lat_srv[r] = S.fetch(tickets[r])[3]
+                    else:
+                        failed += 1
+        submitted = sum(1 for tk in tickets if tk is not None)
+        backlog_srv.append((now, submitted - int(done.sum())))
+        if done.sum() >= next_log:
+            log("served: %d of %d done at %.1f s (backlog %d)" % (int(done.sum()), R, now, backlog_srv[-1][1]))
+            next_log += 200
+        time.sleep(0.005)
+    th.join()
     span_srv = time.perf_counter() - t0
     stats = S.stats()
+    srv_times = S.timing()
     S.close()
-    warm = min(100, R // 2) if R >= 200 else 0
-    p = lambda a, q: float(np.percentile(a[warm:], q))
-    out = {"metric": "served solves/s + p99 latency vs plain", "value": R / span_srv,
-           "unit": "solves/s", "n_gpus": 1, "steps": R, "warmup": warm,
+    log("server time split (s): " + ", ".join("%s %.2f" % kv for kv in srv_times.items()))
+    srv = summarise(done_srv, lat_srv, backlog_srv)
+    pln = summarise(done_plain, lat_plain, backlog_plain)
+    log("served %.2f solves/s (steady %.2f), p50 %.3f s, p99 %.3f s; plain %.2f (steady %.2f), p50 %.3f s, "
+        "p99 %.3f s" % (srv["solves_per_s"], srv["steady_solves_per_s"], srv["p50_s"], srv["p99_s"],
+                        pln["solves_per_s"], pln["steady_solves_per_s"], pln["p50_s"], pln["p99_s"]))
+    out = {"metric": "served solves/s + p99 latency vs plain", "value": srv["steady_solves_per_s"],
+           "unit": "solves/s", "n_gpus": 1, "steps": R, "warmup": w0,
            "ms_per_step": span_srv / R * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "serve_%d_requests_poisson" % R, "offered_rate": lam,
+                      "offered_rate_source": ("frozen: 1.5 x %.1f solves/s (plain, first 20 requests)"
+                                              % (lam / 1.5)) if args.rate > 0 else
+                      "1.5 x this run's plain calibration",
                       "softmax_fraction": float(kind.mean()), "iters": args.iters,
-                      "hbm_budget_GiB": 64, "max_slots": 256, "round_iters": 5},
-           "served": {"solves_per_s": R / span_srv, "p50_s": p(lat_srv, 50), "p99_s": p(lat_srv, 99)},
-           "plain": {"solves_per_s": R / span_plain, "p50_s": p(lat_plain, 50),
-                     "p99_s": p(lat_plain, 99), "calibration_solves_per_s": plain_rate},
-           "server_rounds": stats["rounds"]}
+                      "hbm_budget_GiB": 64, "max_slots": 256, "round_iters": 5,
+                      "steady_window_s": [float(release[w0]), float(release[w1])]},
+           "served": srv, "plain": dict(pln, calibration_solves_per_s=plain_rate),
+           "failed": failed, "server_rounds": stats["rounds"],
+           "server_seconds": {k: round(v, 3) for k, v in srv_times.items()}}
     print(json.dumps(out), flush=True)
 
 
@@ -971,7 +1028,9 @@ def main():
                          "the precision workload's shape, BF16 and FP32; exact-logistic: the logistic "
                          "exact x-update (Newton-CG) beside Algorithm 2 on the default workload")
     ap.add_argument("--instances", type=int, default=512, help="batched: number of problems")
-    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=SERVE_RATE,
+                    help="serve: offered rate in requests/s (0: 1.5 x the plain rate measured first)")
     ap.add_argument("--iters", type=int, default=100, help="batched/serve: outer iterations per problem")
     ap.add_argument("--m-per", type=int, default=0,
                     help="precision: rows per partition (default 100,000; smaller values shrink n too)")

@@ -290,12 +290,14 @@ int bca_batch_get_shape(bca_problem p, int32_t* rows_per_tile, int32_t* rows_per
  * fit (the problem of Sec. 2 with its own data and parameters) run for its
  * max_iters outer iterations.  A scheduler thread admits queued requests in
  * arrival order while a slot is free and the request's device footprint fits
- * hbm_budget_bytes, keeps their ADMM state resident, and advances all resident
- * requests together in rounds of round_iters outer iterations (one-class
- * requests in one batched persistent launch, softmax requests with their own
- * kernels); finished requests are retired between rounds, freeing their slot and
- * memory for waiting ones.  A request's result does not depend on the other
- * requests it shares rounds with.  Submit/poll/fetch/cancel are thread-safe. */
+ * hbm_budget_bytes; a materialiser thread copies each admitted request to the
+ * device and factorises it on a stream of its own while the resident requests
+ * keep running; the scheduler advances all resident requests together in rounds
+ * of round_iters outer iterations (one-class requests in one batched persistent
+ * launch, softmax requests with their own kernels on two streams of the server);
+ * finished requests are retired between rounds, freeing their slot and memory for
+ * waiting ones.  A request's result does not depend on the other requests it
+ * shares rounds with.  Submit/poll/fetch/cancel/stats are thread-safe. */
 
 /* Request states reported by bca_server_poll. */
 enum { BCA_REQ_QUEUED = 0, BCA_REQ_RUNNING = 1, BCA_REQ_DONE = 2, BCA_REQ_FAILED = 3,
@@ -328,8 +330,18 @@ int bca_server_fetch(bca_server s, uint64_t ticket, int32_t* idx, double* x, dou
  * next round boundary.  Errors: BCA_E_NOTFOUND. */
 int bca_server_cancel(bca_server s, uint64_t ticket);
 
-/* Queue length, resident requests, reserved device bytes and rounds run so far. */
+/* Queue length, admitted requests (resident or being materialised), reserved
+ * device bytes and rounds run so far. */
 int bca_server_stats(bca_server s, int32_t* queued, int32_t* running, double* used_bytes, int64_t* rounds);
+
+/* Wall-clock seconds the server's threads have spent so far, per activity, into
+ * seconds[0 .. count-1] (count <= BCA_SRV_TIMES): the rounds' softmax work (issue
+ * and wait), their batched launches, retiring finished requests, materialising
+ * admitted ones, the materialiser waiting for a batched launch to end, and the
+ * scheduler waiting for a materialiser call to end.  Errors: BCA_E_INVALID. */
+enum { BCA_SRV_SOFTMAX = 0, BCA_SRV_BATCHED = 1, BCA_SRV_RETIRE = 2, BCA_SRV_MATERIALISE = 3,
+       BCA_SRV_MAT_WAIT = 4, BCA_SRV_SCHED_WAIT = 5, BCA_SRV_TIMES = 6 };
+int bca_server_timing(bca_server s, double* seconds, int32_t count);
 
 /* Stop the scheduler and release every resident request. */
 int bca_server_destroy(bca_server s);

@@ -35,7 +35,7 @@ EXPORTS = ["bca_create", "bca_set_data", "bca_finalize", "bca_step", "bca_solve"
            "bca_last_error", "bca_topk", "bca_batch_step", "bca_batch_step_noalloc", "bca_batch_solve",
            "bca_batch_autotune", "bca_batch_set_shape", "bca_batch_get_shape",
            "bca_server_create", "bca_server_submit", "bca_server_poll", "bca_server_fetch",
-           "bca_server_cancel", "bca_server_stats", "bca_server_destroy"]
+           "bca_server_cancel", "bca_server_stats", "bca_server_timing", "bca_server_destroy"]
 
 
 class BcaError(RuntimeError):
@@ -96,6 +96,7 @@ def _load():
         "bca_server_fetch": [P, ctypes.c_uint64, P, P, pdbl, pdbl],
         "bca_server_cancel": [P, ctypes.c_uint64],
         "bca_server_stats": [P, pi32, pi32, pdbl, ctypes.POINTER(ctypes.c_int64)],
+        "bca_server_timing": [P, pdbl, i32],
         "bca_server_destroy": [P],
     }
     for name, args in sig.items():
@@ -414,6 +415,13 @@ class Server:
         _check(_lib.bca_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(u),
                                      ctypes.byref(k)))
         return dict(queued=q.value, running=r.value, used_bytes=u.value, rounds=k.value)
+
+    def timing(self):
+        """Seconds per server activity (bca_server_timing)."""
+        t = (ctypes.c_double * 6)()
+        _check(_lib.bca_server_timing(self._h, t, 6))
+        return dict(zip(("softmax", "batched", "retire", "materialise", "materialiser_wait",
+                         "scheduler_wait"), list(t)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -19,9 +19,14 @@
 //   GLOBAL  item (problem): consensus average, exact (z,t) step, top-kappa
 //           s-step, v and u updates, residuals.
 // The wavefronts of the persistent grid take the items of the current phase
-// (largest first: stream items through an atomic counter, solve items
-// round-robin; global items per workgroup through a counter) and meet at a grid
-// barrier between phases.  A problem's results depend only on its own items
+// (largest first: stream items through atomic counters, solve items
+// round-robin; global items per workgroup through counters) and meet at a grid
+// barrier between phases.  Both the counters and the barrier are split over
+// eight groups of workgroups (blockIdx mod 8, the XCD a workgroup is dispatched
+// to): a device-scope atomic on one address serialises every arrival, and with
+// 512 workgroups (2,048 wavefronts) the cooperative-groups grid barrier took
+// 50-70 us and one claim per wavefront on one counter about 20 us, against a few
+// microseconds of work per phase for small problems.  A problem's results depend only on its own items
 // (fixed reduction orders inside each item, tile shape chosen per problem shape,
 // never per batch), so a problem computes the same bits alone and inside any
 // batch.
@@ -33,16 +38,12 @@
 // tiles are otherwise too small to keep enough bytes in flight), which bounds the
 // kernel's register footprint; rows per item is a runtime parameter.
 // The shape of each problem is picked by the autotuner in bca_api.hip.
-#include <hip/hip_cooperative_groups.h>
-
 #include "bca_internal.h"
 #include "global_impl.h"
 #include "prox_impl.h"
 #include "symv_impl.h"
 
 namespace bca {
-
-namespace cg = cooperative_groups;
 
 constexpr int BT = 256;
 constexpr int BW = BT / 64;
@@ -360,6 +361,46 @@ __device__ GlobalArgs global_args_of(const BatchInst& I) {
   return g;
 }
 
+// Grid barrier of the persistent launch (all workgroups are resident: the launch
+// is cooperative).  Workgroup g arrives at the counter of its group g mod 8; the
+// last arrival of a group adds the group to a second counter, and the last group
+// publishes the barrier's number in a generation word that every workgroup polls.
+// Counters only grow (barrier e completes a group at (e + 1) times its size), so
+// no reset is needed within a launch; all start at zero.  Layout (32-bit words,
+// each on its own 128-byte line): group counters at 32 x, x < 8; the group
+// arrivals at 256; the generation at 288.  Visibility: every wavefront waits for
+// its own memory operations; one release fence per workgroup (agent scope) writes
+// the XCD's L2 back before a relaxed arrival; the last arrival of a group
+// acquires the group's arrivals before adding the group to the second counter
+// (acquire-release), the last group stores the generation (release); the others
+// poll with relaxed loads (an acquiring load would invalidate the caches at every
+// poll) and acquire once they see it.
+constexpr int kGroups = kBatchCounterGroups;
+static_assert(kBatchBarWords >= 289, "barrier words");
+
+__device__ __forceinline__ void grid_barrier(unsigned int* bar, unsigned int& epoch) {
+  __builtin_amdgcn_s_waitcnt(0);   // this wavefront's loads and stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned int x = blockIdx.x % kGroups;
+    const unsigned int nx = (gridDim.x + kGroups - 1 - x) / kGroups;   // workgroups in group x
+    const unsigned int ng = gridDim.x < kGroups ? gridDim.x : kGroups;   // groups in use
+    const unsigned int target = epoch + 1;
+    const unsigned int old = __hip_atomic_fetch_add(&bar[32 * x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == target * nx - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const unsigned int g = __hip_atomic_fetch_add(&bar[256], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (g == target * ng - 1) __hip_atomic_store(&bar[288], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    while (__hip_atomic_load(&bar[288], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+      __builtin_amdgcn_s_sleep(8);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  epoch += 1;
+}
+
 // Two workgroups per CU: at most 256 registers per lane (VGPRs and AGPRs).
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(BatchArgs ba) {
   // the widest stream shape's partial sums
@@ -367,12 +408,18 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
   __shared__ double shd[BW * (PSECT + 2)];
   __shared__ TopkShared<BT> tks;
   __shared__ int item_sh;
-  cg::grid_group grid = cg::this_grid();
+  unsigned int epoch = 0;
   int phase = 0;
+  // the workgroup's group (of kGroups) for counters and barrier, and the group's size
+  const int grp = blockIdx.x % kGroups;
+  const int ngrp = (int)gridDim.x < kGroups ? (int)gridDim.x : kGroups;
 
+  // Claims of a phase: group x takes items x, x + ngrp, x + 2 ngrp, ... from its
+  // own counter (counters[kGroups * phase + x]).
   // claims the next item of the current phase (all threads get the same index)
   auto claim = [&]() {
-    if (threadIdx.x == 0) item_sh = (int)atomicAdd(&ba.counters[phase], 1u);
+    if (threadIdx.x == 0)
+      item_sh = grp + ngrp * (int)atomicAdd(&ba.counters[kGroups * phase + grp], 1u);
     __syncthreads();
     const int it = item_sh;
     __syncthreads();
@@ -381,13 +428,13 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
   // The items of the solve and stream phases go to single wavefronts (no
   // workgroup barrier between items, so the 8 wavefronts of a CU overlap their
   // per-item latencies).  Stream items, whose costs vary with the tile shape,
-  // are claimed with an atomic counter; the many small solve items are dealt
+  // are claimed through the group counters; the many small solve items are dealt
   // round-robin over the wavefronts of the grid (largest first), since a claim
   // costs about as much as such an item and the claims of one counter serialise.
   auto claim_wave = [&]() {
     int it = 0;
-    if ((threadIdx.x & 63) == 0) it = (int)atomicAdd(&ba.counters[phase], 1u);
-    return __shfl(it, 0, 64);
+    if ((threadIdx.x & 63) == 0) it = (int)atomicAdd(&ba.counters[kGroups * phase + grp], 1u);
+    return grp + ngrp * __shfl(it, 0, 64);
   };
   const int gwave = blockIdx.x * BW + (threadIdx.x >> 6), nwaves = gridDim.x * BW;
   auto run_stream = [&](const BatchItem* items, int count, int mode, int k_inner, int o) {
@@ -406,7 +453,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
   if (ba.n_prime > 0) {
     run_stream(ba.prime_items, ba.n_prime, 1, 0, 0);
     if (ba.stream_only) return;
-    grid.sync();
+    grid_barrier(ba.bar, epoch);
   }
   for (int o = 0; o < ba.outer; ++o) {
     for (int k = 0; k < ba.inner_max; ++k) {
@@ -417,7 +464,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
         rhs_item(I, w.a, w.b, w.c);
       }
       ++phase;
-      grid.sync();
+      grid_barrier(ba.bar, epoch);
       for (int it = gwave; it < ba.n_symv; it += nwaves) {
         const BatchItem w = ba.symv_items[it];
         const BatchInst& I = ba.inst[w.inst];
@@ -425,7 +472,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
         symv_item(I, w.a, w.b, w.c, w.d);
       }
       ++phase;
-      grid.sync();
+      grid_barrier(ba.bar, epoch);
       for (int it = gwave; it < ba.n_xupd; it += nwaves) {
         const BatchItem w = ba.xupd_items[it];
         const BatchInst& I = ba.inst[w.inst];
@@ -433,9 +480,9 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
         xupd_item(I, w.a, w.b, w.c);
       }
       ++phase;
-      grid.sync();
+      grid_barrier(ba.bar, epoch);
       run_stream(ba.stream_items, ba.n_stream, 0, k, o);
-      grid.sync();
+      grid_barrier(ba.bar, epoch);
     }
     for (int it = claim(); it < ba.count; it = claim()) {
       const BatchInst& I = ba.inst[it];
@@ -444,7 +491,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
       __syncthreads();
     }
     ++phase;
-    grid.sync();
+    grid_barrier(ba.bar, epoch);
   }
 }
 

@@ -70,7 +70,7 @@ struct bca_problem_s {
   std::vector<int64_t> rows, row_off;
   std::vector<int32_t> col_off;
   std::vector<int64_t> fac_off, kmat_off;
-  int nj_max = 0, Gp = 1, nvec = 0;
+  int nj_max = 0, Gp = 1, Gd = 1, nvec = 0;
   int64_t fac_total = 0, kmat_total = 0;
   double shift = 0.0;
   // device buffers
@@ -251,6 +251,7 @@ StreamArgs stream_args(bca_problem P, int mode) {
   a.m_total = P->m_total;
   a.N = P->N;
   a.Gp = P->Gp;
+  a.Gd = P->Gd;
   a.nvec = P->nvec;
   a.n = P->n;
   a.M = P->M;
@@ -673,16 +674,30 @@ int bca_create(const bca_params* prm, void* hip_stream, bca_problem* out) {
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
       cus = prop.multiProcessorCount;
-    const int occ = C > 1 ? mc_occupancy_workgroups(P->dtype, P->n, C)
-                          : stream_occupancy_workgroups(P->dtype, P->nvec, C);
-    int64_t gp = (int64_t)occ * cus / P->N;
     int64_t maxrows = 0;
     for (auto r : P->rows) maxrows = std::max(maxrows, r);
-    // at least one 4-row tile per workgroup; with C > 1 at least 16 tiles, since
-    // a workgroup's partial sums (n x C doubles) would otherwise outweigh the
-    // rows of A it streams
-    gp = std::min<int64_t>(gp, (maxrows + (C > 1 ? 63 : 3)) / (C > 1 ? 64 : 4));
-    P->Gp = (int)std::max<int64_t>(1, gp);
+    if (C > 1 && mc_uses_mfma(P->dtype)) {
+      // MFMA form: about two workgroups per CU in each kernel.  The A^T E kernel
+      // takes row ranges of at least 256 samples, so that a range's partial sums
+      // (kMcStrip x C doubles per strip) stay below a tenth of the A it reads; the
+      // sample-space average kernel writes no partial sums and takes 16-row tiles.
+      const int64_t strips = (P->n + kMcStrip - 1) / kMcStrip;
+      int64_t gp = (2 * (int64_t)cus + P->N * strips - 1) / (P->N * strips);
+      gp = std::min<int64_t>(gp, std::max<int64_t>(1, maxrows / 256));
+      P->Gp = (int)std::max<int64_t>(1, gp);
+      int64_t gd = (2 * (int64_t)cus + P->N - 1) / P->N;
+      gd = std::min<int64_t>(gd, (maxrows + 15) / 16);
+      P->Gd = (int)std::max<int64_t>(1, gd);
+    } else {
+      const int occ = C > 1 ? mc_occupancy_workgroups(P->dtype, P->n, C)
+                            : stream_occupancy_workgroups(P->dtype, P->nvec, C);
+      int64_t gp = (int64_t)occ * cus / P->N;
+      // at least one 4-row tile per workgroup; with C > 1 at least 16 tiles, since
+      // a workgroup's partial sums (n x C doubles) would otherwise outweigh the
+      // rows of A it streams
+      gp = std::min<int64_t>(gp, (maxrows + (C > 1 ? 63 : 3)) / (C > 1 ? 64 : 4));
+      P->Gp = (int)std::max<int64_t>(1, gp);
+    }
   }
   P->loaded.assign(P->N, 0);
 
@@ -853,13 +868,21 @@ int bca_finalize(bca_problem P) {
     if (!P->loaded[i]) return fail(BCA_E_STATE, "partition %d has no data", i);
   double *kbuf = nullptr, *wbuf = nullptr;
   const int64_t kmat_total = P->wood ? P->wkmat_total : P->kmat_total;
-  TRY(dalloc(P, &kbuf, (size_t)kmat_total));
-  int rc = dalloc(P, &wbuf, (size_t)kmat_total);
-  if (rc != BCA_OK) {
-    dfree(P, kbuf);
-    return rc;
-  }
   hipStream_t s = P->stream;
+  // The Gram and factor work space lives only for this call.  It comes from the
+  // stream-ordered allocator: a plain hipFree waits for the whole device, which
+  // would make a finalize on one stream wait for long launches on others (the
+  // serving form finalizes admitted requests while resident ones run).
+  const size_t wbytes = (size_t)std::max<int64_t>(kmat_total, 1) * sizeof(double);
+  if (hipMallocAsync(reinterpret_cast<void**>(&kbuf), wbytes, s) != hipSuccess) {
+    kbuf = nullptr;
+    return fail(BCA_E_OOM, "finalize: work space of %zu bytes", wbytes);
+  }
+  if (hipMallocAsync(reinterpret_cast<void**>(&wbuf), wbytes, s) != hipSuccess) {
+    (void)hipFreeAsync(kbuf, s);
+    (void)hipStreamSynchronize(s);
+    return fail(BCA_E_OOM, "finalize: work space of %zu bytes", wbytes);
+  }
   hipError_t e = hipMemsetAsync(wbuf, 0, (size_t)kmat_total * sizeof(double), s);
   if (e == hipSuccess) e = hipMemsetAsync(P->status, 0, sizeof(int), s);
   GramArgs g{};
@@ -952,9 +975,10 @@ int bca_finalize(bca_problem P) {
   }
   int st = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&st, P->status, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dfree(P, kbuf);
-  dfree(P, wbuf);
+  (void)hipFreeAsync(kbuf, s);
+  (void)hipFreeAsync(wbuf, s);
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
   if (e != hipSuccess) return fail(BCA_E_DEVICE, "finalize: %s", hipGetErrorString(e));
   if (st) return fail(BCA_E_NONFINITE, "finalize: a block matrix K_ij (S_ij) is not positive definite");
   P->finalized = true;
@@ -1272,7 +1296,7 @@ int bca_get_timing(bca_problem P, int32_t kernel_class, int32_t* launches, doubl
 
 int bca_destroy(bca_problem P) {
   if (!P) return BCA_OK;
-  if (P->stream || true) (void)hipStreamSynchronize(P->stream);
+  (void)hipStreamSynchronize(P->stream);
   harvest_timing(P);
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
@@ -1291,6 +1315,17 @@ int bca_topk(const void* z, int32_t dtype, int64_t n, int32_t kappa, int32_t* id
 }
 
 }  // extern "C"
+
+// Library-internal (the serving form): later work of P goes to stream s; the work
+// already queued on P's stream is waited for first.
+namespace bca {
+int set_problem_stream(bca_problem P, hipStream_t s) {
+  if (!P) return fail(BCA_E_INVALID, "null problem");
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  P->stream = s;
+  return BCA_OK;
+}
+}  // namespace bca
 
 // ======================================================================= batched form
 namespace {
@@ -1484,7 +1519,8 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   const size_t off_stream = off_xupd + al(xupd.size() * sizeof(BatchItem));
   const size_t off_prime = off_stream + al(stream.size() * sizeof(BatchItem));
   const size_t off_cnt = off_prime + al(primei.size() * sizeof(BatchItem));
-  const size_t total = off_cnt + al((size_t)std::max(phases, 1) * sizeof(unsigned int));
+  const size_t n_cnt = (size_t)std::max(phases, 1) * kBatchCounterGroups + kBatchBarWords;
+  const size_t total = off_cnt + al(n_cnt * sizeof(unsigned int));
   char* base = nullptr;
   if (dev) {
     if (total > cap)
@@ -1512,8 +1548,8 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     HIP_TRY(hipMemcpyAsync(base + off_stream, stream.data(), stream.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   if (!primei.empty())
     HIP_TRY(hipMemcpyAsync(base + off_prime, primei.data(), primei.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
-  // phase counters start at zero (a fill kernel rather than a memset node)
-  HIP_TRY(launch_zero_u32(reinterpret_cast<unsigned int*>(base + off_cnt), std::max(phases, 1), s));
+  // phase counters and barrier words start at zero (a fill kernel rather than a memset node)
+  HIP_TRY(launch_zero_u32(reinterpret_cast<unsigned int*>(base + off_cnt), (int)n_cnt, s));
   BatchArgs a{};
   a.inst = reinterpret_cast<const BatchInst*>(base + off_desc);
   a.count = count;
@@ -1530,6 +1566,7 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   a.outer = outer_max;
   a.inner_max = inner_max;
   a.counters = reinterpret_cast<unsigned int*>(base + off_cnt);
+  a.bar = a.counters + (size_t)std::max(phases, 1) * kBatchCounterGroups;
   a.stream_only = stream_only ? 1 : 0;
   const int grid = batch_grid_size();
   if (grid < 1) return fail(BCA_E_DEVICE, "batched kernel does not fit on this device");

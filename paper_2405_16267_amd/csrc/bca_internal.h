@@ -130,6 +130,8 @@ struct StreamArgs {
   double* rowbuf;          // m_total x C (C > 1): sample-space averages, then e
   int64_t m_total;
   int N, Gp, nvec, n, M, C, loss;
+  int Gd;                  // C > 1, FP32 / BF16 storage: workgroups per partition of the
+                           // sample-space average kernel (16-row tiles, no partial sums)
   double inv_M, rho_l;
   int mode;                // 0: inner iteration; 1: prime (e from stored state, no prox);
                            // 2, 3: gradient and Hessian-vector passes of the logistic
@@ -152,10 +154,19 @@ struct ObjArgs {
 
 struct Problem;  // host-side problem (bca_api.hip)
 
+// Later work of the problem goes to stream s (the work queued on its current
+// stream is waited for first); used by the serving form, which finalizes admitted
+// requests on a stream of their own.
+int set_problem_stream(bca_problem P, hipStream_t s);
+
 // Launchers (host side).  Each returns hipSuccess or the launch error.
 hipError_t launch_stream(const StreamArgs& a, int dtype, hipStream_t s);
 // Resident workgroups per CU of the multi-class streaming kernels (C > 1).
 int mc_occupancy_workgroups(int dtype, int n, int C);
+// C > 1 with FP32 / BF16 storage: the streaming pass runs on MFMA (stream_mc.hip);
+// its A^T E kernel covers 128 features per workgroup.
+inline bool mc_uses_mfma(int dtype) { return dtype != BCA_F64; }
+constexpr int kMcStrip = 128;
 hipError_t launch_objective(const ObjArgs& a, int dtype, hipStream_t s);
 // C > 1 (softmax) forms of the two passes (stream_mc.hip)
 bool mc_supported(int n, int C);
@@ -400,9 +411,13 @@ struct BatchArgs {
   const BatchItem* prime_items;    // stream items of problems whose partial sums are stale
   int n_prime;
   int outer, inner_max;
-  unsigned int* counters;          // one work counter per phase, zeroed before the launch
+  unsigned int* counters;          // 8 work counters per phase (one per group of
+                                   // workgroups), zeroed before the launch
+  unsigned int* bar;               // grid barrier words (kBatchBarWords), zeroed before the launch
   int stream_only;                 // 1: run only the prime phase (tile-shape timing)
 };
+constexpr int kBatchCounterGroups = 8;
+constexpr int kBatchBarWords = 320;
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int* p, int count, hipStream_t s);   // p[0..count) = 0
 int batch_grid_size();            // co-resident workgroups of the batched kernel

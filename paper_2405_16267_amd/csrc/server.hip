@@ -1,17 +1,20 @@
 // Serving form: a request loop with continuous batching.
 //
 // Requests (sparse-fit problems of different sizes) are submitted from host
-// memory and queued.  A scheduler thread admits queued requests, in arrival
+// memory and queued.  The scheduler thread admits queued requests, in arrival
 // order, while a slot is free and the request's device footprint fits the HBM
-// budget; an admitted request gets a resident problem (data copied once, Gram
-// and factorisation, zero state).  Every scheduler round advances ALL resident
-// requests together -- one-class requests by `round_iters` outer iterations of
-// the batched persistent launch, softmax requests by the same number of
-// iterations of their own kernels, spread over three extra streams so that
-// the kernels of different requests overlap -- then retires the finished ones (results
-// copied to host, device memory released) so that waiting requests can enter
-// between rounds.  A request's arithmetic never depends on the other requests
-// it shares rounds with, so its result is the same alone and in any mix.
+// budget, and hands them to a materialiser thread, which builds each admitted
+// request's resident problem (data copied once, Gram and factorisation, zero
+// state) on a stream of its own while the resident requests keep running.  A
+// materialised request joins the resident set at the start of the next round.
+// Every scheduler round advances ALL resident requests together -- one-class
+// requests by `round_iters` outer iterations of the batched persistent launch,
+// softmax requests by the same number of iterations of their own kernels,
+// spread over two extra streams so that the kernels of different requests
+// overlap -- then retires the finished ones (results copied to host, device
+// memory released) so that waiting requests can enter.  A request's arithmetic
+// never depends on the other requests it shares rounds with, so its result is
+// the same alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +31,7 @@
 #include <vector>
 
 #include "bca.h"
+#include "bca_internal.h"
 
 namespace {
 
@@ -50,6 +54,7 @@ struct Request {
   int state = RQ_QUEUED;
   std::atomic<bool> cancel{false};   // set by bca_server_cancel, read by the scheduler
   bca_problem prob = nullptr;
+  int issued = 0;                    // outer iterations issued by the rounds so far
   size_t bytes = 0;
   std::vector<int32_t> support;
   std::vector<double> coef;
@@ -83,61 +88,137 @@ size_t footprint(const bca_params& p, const std::vector<int64_t>& rows) {
 
 }  // namespace
 
-// Softmax requests run their own kernels; they are spread over a few extra
-// streams (default priority) so that the kernels of different requests, each
-// too small to fill the GPU, overlap.
-constexpr int kSideStreams = 3;
+// Softmax requests run their own kernels; they are spread over two extra
+// streams so that the kernels of different requests, each too small to fill the
+// GPU, overlap.  The server's own streams (these and the materialiser's) are
+// non-blocking, at the default priority: the rounds may run on the legacy
+// default stream (the caller's), and a blocking stream would wait for each round
+// launched before its every command (and each round for the stream's last
+// command), which would leave the materialiser one command per round.  With the
+// caller's stream, that makes four streams, one per hardware queue of a process.
+//
+// The batched launch is cooperative, with a grid sized to fill every CU, and its
+// grid barriers need all of its workgroups resident at once: no other kernel may
+// run beside it.  So the softmax kernels of a round finish before it starts, and
+// the materialiser's device work (each library call, which returns with its
+// stream drained) and the batched launch hold `gpu_mu` in turn.
+constexpr int kSideStreams = 2;
 
 struct bca_server_s {
   size_t budget = 0, used = 0;
   int max_slots = 1, round_iters = 1;
   int device = 0;
   hipStream_t stream = nullptr;
-  hipStream_t side[kSideStreams] = {nullptr, nullptr, nullptr};
+  hipStream_t side[kSideStreams] = {nullptr, nullptr};
+  hipStream_t mstream = nullptr;   // the materialiser's stream
   uint64_t side_next = 0;
   std::mutex mu;
-  std::condition_variable cv;
-  std::deque<Request*> queue;
-  std::vector<Request*> active;
+  std::mutex gpu_mu;               // the batched launch, or one materialiser call
+  std::condition_variable cv;      // wakes the scheduler
+  std::condition_variable mcv;     // wakes the materialiser
+  bool kick = false;               // something for the scheduler (submit, cancel, ready)
+  std::deque<Request*> queue;      // submitted, not admitted
+  std::deque<Request*> to_mat;     // admitted, waiting for the materialiser
+  int materialising = 0;           // taken by the materialiser, not finished
+  std::vector<Request*> ready;     // materialised, joining at the next round
+  std::vector<Request*> active;    // resident
   std::map<uint64_t, std::unique_ptr<Request>> all;
+  std::map<int64_t, std::pair<int, int>> shapes;   // tuned batched tile shapes (materialiser only)
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker;
+  std::thread worker, mat_worker;
   // statistics
   int64_t rounds = 0;
   double busy_s = 0;
+  double times[BCA_SRV_TIMES] = {0, 0, 0, 0, 0, 0};   // guarded by mu
 };
 
 namespace {
 
-void finish(bca_server_s* S, Request* r, int state, const std::string& err) {
+// Release a request's device problem and host copy.  Called without the server
+// lock (bca_destroy waits for the problem's stream and frees device memory).
+void release(Request* r) {
   if (r->prob) {
     bca_destroy(r->prob);
     r->prob = nullptr;
   }
-  r->state = state;
-  r->err = err;
-  r->t_done = now_s();
-  S->used -= r->bytes;
   r->A.clear();
   r->b.clear();
   r->A.shrink_to_fit();
   r->b.shrink_to_fit();
 }
 
-// Create, load and finalize the resident problem of an admitted request.
+// Final state of a request; with the server lock held.
+void settle(bca_server_s* S, Request* r, int state, const std::string& err) {
+  r->state = state;
+  r->err = err;
+  r->t_done = now_s();
+  S->used -= r->bytes;
+}
+
+// Create, load and finalize the resident problem of an admitted request on the
+// materialiser's stream, then move it to the stream its rounds run on.
+void add_time(bca_server_s* S, int k, double dt) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->times[k] += dt;
+}
+
+// gpu_mu for one materialiser call, with the time spent waiting for it recorded
+struct GpuTurn {
+  bca_server_s* S;
+  std::unique_lock<std::mutex> lk;
+  explicit GpuTurn(bca_server_s* s, int wait_slot) : S(s), lk(s->gpu_mu, std::defer_lock) {
+    const double t = now_s();
+    lk.lock();
+    add_time(S, wait_slot, now_s() - t);
+  }
+};
+
 int materialise(bca_server_s* S, Request* r) {
   bca_params p = r->params;
   p.rows = r->rows.data();
-  hipStream_t st = S->stream;
-  if (p.loss == BCA_LOSS_SOFTMAX && S->side[0]) st = S->side[S->side_next++ % kSideStreams];
-  int rc = bca_create(&p, st, &r->prob);
+  int rc = BCA_OK;
+  {
+    GpuTurn g(S, BCA_SRV_MAT_WAIT);
+    rc = bca_create(&p, S->mstream, &r->prob);
+  }
   if (rc != BCA_OK) return rc;
   for (int i = 0; i < p.n_partitions; ++i) {
+    GpuTurn g(S, BCA_SRV_MAT_WAIT);
     rc = bca_set_data(r->prob, i, r->A[i].data(), p.n_features, r->b[i].data(), BCA_MEM_HOST);
     if (rc != BCA_OK) return rc;
   }
-  return bca_finalize(r->prob);
+  {
+    GpuTurn g(S, BCA_SRV_MAT_WAIT);
+    rc = bca_finalize(r->prob);
+    // one-class requests: the batched pass's tile shape, tuned once per class of
+    // requests (storage type, 16-byte chunks per row rounded to a power of two,
+    // log2 of the tallest partition: the autotuner's own grouping) and reused
+    if (rc == BCA_OK && p.loss != BCA_LOSS_SOFTMAX) {
+      const int vec = p.a_dtype == BCA_F64 ? 2 : (p.a_dtype == BCA_F32 ? 4 : 8);
+      const int nvec = (p.n_features + vec - 1) / vec;
+      int nc = 1;
+      while (nc < 8 && 64 * nc < nvec) nc *= 2;
+      int64_t mx = 0;
+      for (int i = 0; i < p.n_partitions; ++i) mx = std::max<int64_t>(mx, p.rows[i]);
+      int lg = 0;
+      while ((int64_t(1) << (lg + 1)) <= mx) ++lg;
+      const int64_t key = ((int64_t)p.a_dtype << 32) | ((int64_t)nc << 16) | lg;
+      auto it = S->shapes.find(key);
+      if (it != S->shapes.end()) {
+        rc = bca_batch_set_shape(r->prob, it->second.first, it->second.second);
+      } else {
+        rc = bca_batch_autotune(&r->prob, 1, S->mstream);
+        int rt = 0, ri = 0;
+        if (rc == BCA_OK) rc = bca_batch_get_shape(r->prob, &rt, &ri);
+        if (rc == BCA_OK) S->shapes[key] = {rt, ri};
+      }
+    }
+  }
+  if (rc != BCA_OK) return rc;
+  hipStream_t st = S->stream;
+  if (p.loss == BCA_LOSS_SOFTMAX) st = S->side[S->side_next++ % kSideStreams];
+  return bca::set_problem_stream(r->prob, st);
 }
 
 int collect(Request* r) {
@@ -152,15 +233,52 @@ int collect(Request* r) {
   return rc;
 }
 
+void materialiser(bca_server_s* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->mcv.wait(lk, [&] { return S->stop || !S->to_mat.empty(); });
+      if (S->stop) break;
+      r = S->to_mat.front();
+      S->to_mat.pop_front();
+      S->materialising += 1;
+    }
+    int rc = BCA_OK;
+    std::string msg;
+    if (!r->cancel) {
+      const double t = now_s();
+      rc = materialise(S, r);
+      if (rc != BCA_OK) msg = bca_last_error();
+      add_time(S, BCA_SRV_MATERIALISE, now_s() - t);
+    }
+    const bool drop = r->cancel || rc != BCA_OK;
+    if (drop) release(r);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->materialising -= 1;
+      if (r->cancel)
+        settle(S, r, RQ_CANCELLED, "cancelled");
+      else if (rc != BCA_OK)
+        settle(S, r, RQ_FAILED, msg);
+      else
+        S->ready.push_back(r);
+      S->kick = true;
+    }
+    S->cv.notify_all();
+  }
+}
+
 void scheduler(bca_server_s* S) {
   (void)hipSetDevice(S->device);
   for (;;) {
-    std::vector<Request*> admitted;
+    std::vector<Request*> act;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv.wait_for(lk, std::chrono::milliseconds(S->active.empty() && S->queue.empty() ? 50 : 0), [&] {
-        return S->stop || !S->queue.empty() || !S->active.empty();
-      });
+      if (S->active.empty() && S->ready.empty())
+        S->cv.wait_for(lk, std::chrono::milliseconds(50), [&] { return S->stop || S->kick; });
+      S->kick = false;
       if (S->stop) break;
       // cancelled requests still waiting leave the queue
       for (auto it = S->queue.begin(); it != S->queue.end();) {
@@ -173,59 +291,63 @@ void scheduler(bca_server_s* S) {
         }
       }
       // admission in arrival order: a free slot and room in the HBM budget
-      while (!S->queue.empty() && (int)(S->active.size() + admitted.size()) < S->max_slots) {
+      bool admitted = false;
+      auto slots = [&] {
+        return (int)(S->active.size() + S->ready.size() + S->to_mat.size()) + S->materialising;
+      };
+      while (!S->queue.empty() && slots() < S->max_slots) {
         Request* r = S->queue.front();
         if (S->used + r->bytes > S->budget) break;
         S->queue.pop_front();
         S->used += r->bytes;
         r->state = RQ_RUNNING;
         r->t_admit = now_s();
-        admitted.push_back(r);
+        S->to_mat.push_back(r);
+        admitted = true;
       }
-    }
-    const double t0 = now_s();
-    for (Request* r : admitted) {
-      const int rc = materialise(S, r);
-      std::lock_guard<std::mutex> lk(S->mu);
-      if (rc != BCA_OK) {
-        finish(S, r, RQ_FAILED, bca_last_error());
-      } else {
-        S->active.push_back(r);
-      }
-    }
-    std::vector<Request*> act;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
+      if (admitted) S->mcv.notify_all();
+      // materialised requests join the resident set
+      for (Request* r : S->ready) S->active.push_back(r);
+      S->ready.clear();
       act = S->active;
     }
     if (act.empty()) continue;
+    const double t0 = now_s();
     // one round: every resident request advances by round_iters outer iterations
     std::vector<bca_problem> one_class;
     std::vector<Request*> oc_req;
     std::vector<std::pair<Request*, std::string>> failed;
+    // (the iteration counts are tracked on the host: no device read-back, which
+    // would wait for the request's stream, inside the round)
+    double tm = now_s();
     for (Request* r : act) {
       if (r->cancel) continue;
+      const int k = std::min(S->round_iters, r->params.max_iters - r->issued);
       if (r->params.loss == BCA_LOSS_SOFTMAX) {
-        int done_it = 0;
-        bca_get_residuals(r->prob, nullptr, nullptr, nullptr, &done_it);
-        const int k = std::min(S->round_iters, r->params.max_iters - done_it);
         if (k > 0 && bca_step(r->prob, k, nullptr) != BCA_OK) failed.push_back({r, bca_last_error()});
       } else {
         one_class.push_back(r->prob);
         oc_req.push_back(r);
       }
+      r->issued += std::max(k, 0);
     }
+    for (int q = 0; q < kSideStreams; ++q)
+      if (S->side[q]) (void)hipStreamSynchronize(S->side[q]);
+    add_time(S, BCA_SRV_SOFTMAX, now_s() - tm);
     if (!one_class.empty()) {
+      GpuTurn g(S, BCA_SRV_SCHED_WAIT);
+      tm = now_s();
       if (bca_batch_step(one_class.data(), (int)one_class.size(), S->round_iters, S->stream) != BCA_OK) {
         const std::string msg = bca_last_error();
         for (Request* r : oc_req) failed.push_back({r, msg});
       }
+      (void)hipStreamSynchronize(S->stream);
+      add_time(S, BCA_SRV_BATCHED, now_s() - tm);
     }
-    (void)hipStreamSynchronize(S->stream);
-    for (int q = 0; q < kSideStreams; ++q)
-      if (S->side[q]) (void)hipStreamSynchronize(S->side[q]);
+    tm = now_s();
     // retire finished, failed and cancelled requests
-    std::vector<Request*> keep;
+    std::vector<Request*> keep, gone;
+    std::vector<std::pair<int, std::string>> outcome;
     for (Request* r : act) {
       bool bad = false;
       std::string msg;
@@ -234,29 +356,28 @@ void scheduler(bca_server_s* S) {
           bad = true;
           msg = f.second;
         }
-      int it = 0;
-      if (!bad && !r->cancel) bca_get_residuals(r->prob, nullptr, nullptr, nullptr, &it);
-      std::lock_guard<std::mutex> lk(S->mu);
+      const int it = r->issued;
       if (r->cancel) {
-        finish(S, r, RQ_CANCELLED, "cancelled");
+        outcome.push_back({RQ_CANCELLED, "cancelled"});
       } else if (bad) {
-        finish(S, r, RQ_FAILED, msg);
+        outcome.push_back({RQ_FAILED, msg});
       } else if (it >= r->params.max_iters) {
         const int rc = collect(r);
-        finish(S, r, rc == BCA_OK ? RQ_DONE : RQ_FAILED, rc == BCA_OK ? "" : bca_last_error());
+        outcome.push_back({rc == BCA_OK ? RQ_DONE : RQ_FAILED, rc == BCA_OK ? "" : bca_last_error()});
       } else {
         keep.push_back(r);
+        continue;
       }
+      gone.push_back(r);
+      release(r);
     }
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      // requests admitted while this round ran are not in `act`; keep them
-      std::vector<Request*> merged = keep;
-      for (Request* r : S->active)
-        if (std::find(act.begin(), act.end(), r) == act.end()) merged.push_back(r);
-      S->active = merged;
+      for (size_t q = 0; q < gone.size(); ++q) settle(S, gone[q], outcome[q].first, outcome[q].second);
+      S->active = keep;
       S->rounds += 1;
       S->busy_s += now_s() - t0;
+      S->times[BCA_SRV_RETIRE] += now_s() - tm;
     }
     S->cv.notify_all();
   }
@@ -278,14 +399,16 @@ int bca_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t round_
     delete S;
     return BCA_E_DEVICE;
   }
-  for (int q = 0; q < kSideStreams; ++q) {
-    if (hipStreamCreate(&S->side[q]) != hipSuccess) {
-      for (int j = 0; j < q; ++j) (void)hipStreamDestroy(S->side[j]);
+  hipStream_t* mine[kSideStreams + 1] = {&S->side[0], &S->side[1], &S->mstream};
+  for (int q = 0; q <= kSideStreams; ++q) {
+    if (hipStreamCreateWithFlags(mine[q], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < q; ++j) (void)hipStreamDestroy(*mine[j]);
       delete S;
       return BCA_E_DEVICE;
     }
   }
   S->worker = std::thread(scheduler, S);
+  S->mat_worker = std::thread(materialiser, S);
   *out = S;
   return BCA_OK;
 }
@@ -319,6 +442,7 @@ int bca_server_submit(bca_server S, const bca_params* params, const void* const*
   *ticket = r->ticket;
   S->queue.push_back(r.get());
   S->all[r->ticket] = std::move(r);
+  S->kick = true;
   S->cv.notify_all();
   return BCA_OK;
 }
@@ -354,6 +478,7 @@ int bca_server_cancel(bca_server S, uint64_t ticket) {
   auto it = S->all.find(ticket);
   if (it == S->all.end()) return BCA_E_NOTFOUND;
   it->second->cancel = true;
+  S->kick = true;
   S->cv.notify_all();
   return BCA_OK;
 }
@@ -362,9 +487,17 @@ int bca_server_stats(bca_server S, int32_t* queued, int32_t* running, double* us
   if (!S) return BCA_E_INVALID;
   std::lock_guard<std::mutex> lk(S->mu);
   if (queued) *queued = (int32_t)S->queue.size();
-  if (running) *running = (int32_t)S->active.size();
+  // admitted requests: resident, materialised, or being materialised
+  if (running) *running = (int32_t)(S->active.size() + S->ready.size() + S->to_mat.size()) + S->materialising;
   if (used_bytes) *used_bytes = (double)S->used;
   if (rounds) *rounds = S->rounds;
+  return BCA_OK;
+}
+
+int bca_server_timing(bca_server S, double* seconds, int32_t count) {
+  if (!S || !seconds || count < 0 || count > BCA_SRV_TIMES) return BCA_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (int k = 0; k < count; ++k) seconds[k] = S->times[k];
   return BCA_OK;
 }
 
@@ -375,11 +508,14 @@ int bca_server_destroy(bca_server S) {
     S->stop = true;
   }
   S->cv.notify_all();
+  S->mcv.notify_all();
   if (S->worker.joinable()) S->worker.join();
-  for (Request* r : S->active)
-    if (r->prob) bca_destroy(r->prob);
+  if (S->mat_worker.joinable()) S->mat_worker.join();
+  for (auto& kv : S->all)
+    if (kv.second->prob) bca_destroy(kv.second->prob);
   for (int q = 0; q < kSideStreams; ++q)
     if (S->side[q]) (void)hipStreamDestroy(S->side[q]);
+  if (S->mstream) (void)hipStreamDestroy(S->mstream);
   delete S;
   return BCA_OK;
 }

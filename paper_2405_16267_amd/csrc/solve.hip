@@ -53,8 +53,11 @@ __global__ __launch_bounds__(256) void symv_kernel(SolveArgs a) {
   int I, J;
   tri_tile(t, &I, &J);
   const int T = (nj + PT - 1) / PT, tmax = (a.nj_max + PT - 1) / PT;
+  // with C right-hand sides, the grid's z index takes one of them, so that the C
+  // products of a tile run in parallel (the tile is read C times, mostly from cache)
+  const int cb = a.C > 1 ? (int)blockIdx.z : 0, ce = a.C > 1 ? cb + 1 : 1;
   symv_tile<NTL>(a.kinv + a.fac_off[bid] + (int64_t)t * PT_ELEMS, a.rhs + ((int64_t)part * a.n + c0) * a.C,
-            nj, a.C, I, J, T, a.ypart + (int64_t)bid * tmax * tmax * PT * a.C);
+            nj, a.C, I, J, T, a.ypart + (int64_t)bid * tmax * tmax * PT * a.C, cb, ce);
 }
 
 // one thread per element (i, c) of the block's n_j x C vector; ASSIGN: x = y
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void xupd_kernel(SolveArgs a) {
 // ordinary loads.
 static void symv_launch(const SolveArgs& a, hipStream_t s, bool ntl) {
   const int64_t tiles = ptile_count(a.nj_max);
-  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M);
+  dim3 g2((unsigned)((tiles + 3) / 4), a.N * a.M, a.C > 1 ? a.C : 1);
   const double bytes = (double)tiles * PT_ELEMS * 8.0 * a.N * a.M;
   if (ntl && bytes > (double)(1ll << 30))
     hipLaunchKernelGGL(symv_kernel<true>, g2, dim3(256), 0, s, a);

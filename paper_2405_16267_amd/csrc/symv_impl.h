@@ -17,7 +17,8 @@ namespace bca {
 typedef double symv_d2 __attribute__((ext_vector_type(2)));
 
 // tile: this tile's 4096 doubles; r: the block's right-hand sides (n_j x C,
-// feature-major); ys: the block's slots, slot (R, S) at ys + (R T + S) 64 C.
+// feature-major); ys: the block's slots, slot (R, S) at ys + (R T + S) 64 C;
+// right-hand sides cb .. ce - 1 (all C when ce < 0).
 // Lane l = 8 a + b holds rows 16 q + 2 a + h (q < 4, h < 2) and columns
 // 8 b .. 8 b + 7 of the tile.  Row sums are reduced over the 8 lanes of equal a
 // (DPP), column sums over the 8 lanes of equal b.  NTL: nontemporal tile loads,
@@ -25,7 +26,8 @@ typedef double symv_d2 __attribute__((ext_vector_type(2)));
 // still cached from the previous product).
 template <bool NTL = false>
 __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const double* __restrict__ r,
-                                          int nj, int C, int I, int J, int T, double* __restrict__ ys) {
+                                          int nj, int C, int I, int J, int T, double* __restrict__ ys,
+                                          int cb = 0, int ce = -1) {
   const int lane = threadIdx.x & 63;
   const int a = lane >> 3, b = lane & 7;
   const bool diag = I == J;
@@ -41,7 +43,8 @@ __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const
         p[q][k] = tp[(q * 8 + k) * 64];
     }
   const int colJ = PT * J + 8 * b, rowI = PT * I + 2 * a;
-  for (int c = 0; c < C; ++c) {
+  if (ce < 0) ce = C;
+  for (int c = cb; c < ce; ++c) {
     // indices past n_j are clamped: the tile is zero there
     double rj[8];
 #pragma unroll

@@ -120,6 +120,58 @@ def test_wide_row_launch_shapes_match_oracle(dtype, n, M, loss, seed):
     P.close()
 
 
+# ------------------------------------------------------------------ softmax, MFMA streaming pass
+# FP32 and BF16 storage run the multi-class pass on MFMA: the sample-space average
+# kernel picks (wavefronts x steps of 32 features) from n -- n = 100 -> 4 x 1,
+# 250 -> 4 x 2, 500 -> 4 x 4, 1,000 -> 4 x 8, 2,000 -> 8 x 8 -- and the A^T E
+# kernel covers strips of 128 features (a ragged last strip unless 128 divides n)
+# and row ranges of at least 256 samples (several per partition here).  Rows are
+# at least twice the block width, so that K_ij stays well conditioned.
+MC_SHAPES = [
+    # dtype, n, C, feature blocks, rows, seed
+    ("f32", 100, 3, 2, [700, 531], 91),
+    ("f32", 250, 16, 2, [1100, 1037], 92),
+    ("f32", 500, 10, 2, [1100, 613], 93),
+    ("f32", 1000, 10, 2, [1100, 1037], 94),
+    ("f32", 2000, 5, 4, [1100, 1037], 95),
+    ("bf16", 1000, 10, 2, [1100, 1037], 96),
+    ("bf16", 1930, 7, 4, [1100, 1037], 97),
+]
+
+
+@pytest.mark.parametrize("dtype,n,C,M,rows,seed", MC_SHAPES,
+                         ids=["%s-n%d-C%d" % (s[0], s[1], s[2]) for s in MC_SHAPES])
+def test_softmax_mfma_launch_shapes_match_oracle(dtype, n, C, M, rows, seed):
+    bca = _bca()
+    K = 3
+    w = datagen.softmax_workload(seed, N=2, m_per=rows, n=n, C=C, kappa=6, k_true=6, n_blocks=M,
+                                 dtype=dtype, max_iters=K)
+    tol = 1e-5
+    P = bca.Problem("softmax", w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
+                    rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters, max_iters=w.max_iters,
+                    dtype=dtype, n_classes=C)
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    o = oracle.BiCADMM([datagen.widen(a) for a in w.A], w.b, w.loss, w.n_blocks, w.kappa,
+                       w.gamma, w.rho_c, w.rho_b, w.rho_l, n_classes=C)
+    for k in range(K):
+        P.step(1)
+        o.iterate(1, w.inner_iters)
+        st = o.state
+        close_vec(P.get_vector(bca.VEC_Z), st.z, tol, "z, iteration %d" % (k + 1))
+        for i in range(w.N):
+            close_vec(P.get_vector(bca.VEC_X, i), st.x[i], tol, "x_%d, iteration %d" % (i, k + 1))
+            close_vec(P.get_vector(bca.VEC_OMEGA, i), st.omega[i], tol, "omega_%d" % i)
+            close_vec(P.get_vector(bca.VEC_NU, i), st.nu[i], tol, "nu_%d" % i)
+    if o.topk_margin() > 100 * tol * float(np.max(np.abs(o.state.z))):
+        assert np.array_equal(P.support(), o.support())
+        assert_coef_close(P.coef(), o.coef(), tol)
+        f, fo = P.objective(), o.objective(o.coef())
+        assert abs(f - fo) <= tol * abs(fo)
+    P.close()
+
+
 # ------------------------------------------------------------------ precision workload, sampled
 @pytest.fixture(scope="module")
 def precision_data():

@@ -168,10 +168,13 @@ def batched_bench(args):
         shapes[str(P.batch_shape())] = shapes.get(str(P.batch_shape()), 0) + 1
     log("autotune %.1f s, shapes %s" % (tune_s, shapes))
     torch.cuda.synchronize()
+    bca.batch_set_tracing(True)
     t0 = time.perf_counter()
     bca.batch_solve(probs)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    phase_us, _ = bca.batch_get_tracing()
+    bca.batch_set_tracing(False)
     a_bytes = sum(sum(w.rows) * w.n * 4 for w in ws)
     fac_bytes = 0
     for w in ws:
@@ -192,7 +195,11 @@ def batched_bench(args):
                       "sum_A_GB": a_bytes / 1e9},
            "admm_iter_per_s": sum(its) / el,
            "hbm_gbps_algorithmic": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS,
-           "setup_s": setup_s, "autotune_s": tune_s, "shapes": shapes}
+           "setup_s": setup_s, "autotune_s": tune_s, "shapes": shapes,
+           # per inner iteration (global: per outer iteration), each with its grid barrier
+           "phase_us": {k: round(v / (inner if k in ("rhs", "symv", "xupd", "stream") else
+                                      (args.iters if k == "global" else 1)), 1)
+                        for k, v in phase_us.items()}}
     print(json.dumps(out), flush=True)
 
 

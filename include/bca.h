@@ -270,10 +270,27 @@ int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream);
  * batched partial sums. */
 int bca_batch_step_noalloc(bca_problem* probs, int32_t count, int32_t outer_iters, void* hip_stream);
 
+/* Phase tracing of the batched launches (bca_batch_step, bca_batch_solve,
+ * bca_batch_step_noalloc; not the autotuner's timing launches).  While on, every
+ * launch records when each of its phases ends -- one timestamp per grid barrier,
+ * taken by one thread from the GPU's 100 MHz real-time counter -- and the
+ * microseconds are summed per phase kind: the re-derivation pass of problems
+ * whose partial sums are stale (PRIME), and per inner iteration the right-hand
+ * sides (RHS), the symmetric products (SYMV), the x update (XUPD) and the
+ * streaming pass (STREAM), and the global steps (GLOBAL).  A phase's time
+ * includes the grid barrier that ends it.  Turning tracing on clears the sums.
+ * Tracing needs (phases + 1) x 8 more bytes of launch scratch. */
+enum { BCA_BP_PRIME = 0, BCA_BP_RHS = 1, BCA_BP_SYMV = 2, BCA_BP_XUPD = 3, BCA_BP_STREAM = 4,
+       BCA_BP_GLOBAL = 5, BCA_BP_KINDS = 6 };
+int bca_batch_set_tracing(int32_t on);
+/* Summed microseconds per phase kind into us[0 .. count - 1] (count <= BCA_BP_KINDS)
+ * and the number of traced launches.  Errors: BCA_E_INVALID. */
+int bca_batch_get_tracing(double* us, int32_t count, int64_t* launches);
+
 /* Tile-shape autotuner of the batched streaming pass: groups the problems by
  * (storage type, row length, rows per partition), times every candidate shape
  * (rows per wavefront tile 1/2/4, and 8 for rows of at most 64 16-byte chunks,
- * x rows per work item 64/256/1024; a work item is one wavefront's chunk of rows)
+ * x rows per work item 16/32/64/256/1024; a work item is one wavefront's chunk of rows)
  * on each group
  * with a state-preserving streaming pass, and keeps the fastest per group.  The
  * ADMM state is not modified. */

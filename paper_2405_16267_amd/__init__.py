@@ -8,7 +8,8 @@ when libbca.so has not been built (there is no CPU fallback).  The build step
 _BINDING_NAMES = {"BcaError", "Problem", "topk", "lib", "LIB_PATH", "EXPORTS", "VEC_X", "VEC_U",
                   "VEC_Z", "VEC_S", "VEC_OMEGA", "VEC_NU", "VEC_TV", "KC_STREAM", "KC_SOLVE",
                   "KC_GLOBAL", "KC_GRAM", "KC_FACTOR", "Params", "batch_step", "batch_step_noalloc",
-                  "batch_solve", "batch_autotune", "Server", "REQ_QUEUED", "REQ_RUNNING",
+                  "batch_solve", "batch_autotune", "batch_set_tracing", "batch_get_tracing",
+                  "BATCH_PHASES", "Server", "REQ_QUEUED", "REQ_RUNNING",
                   "REQ_DONE", "REQ_FAILED", "REQ_CANCELLED"}
 
 __all__ = sorted(_BINDING_NAMES)

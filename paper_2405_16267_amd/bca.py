@@ -34,6 +34,7 @@ EXPORTS = ["bca_create", "bca_set_data", "bca_finalize", "bca_step", "bca_solve"
            "bca_set_state", "bca_get_inverse", "bca_set_timing", "bca_get_timing", "bca_destroy",
            "bca_last_error", "bca_topk", "bca_batch_step", "bca_batch_step_noalloc", "bca_batch_solve",
            "bca_batch_autotune", "bca_batch_set_shape", "bca_batch_get_shape",
+           "bca_batch_set_tracing", "bca_batch_get_tracing",
            "bca_server_create", "bca_server_submit", "bca_server_poll", "bca_server_fetch",
            "bca_server_cancel", "bca_server_stats", "bca_server_timing", "bca_server_destroy"]
 
@@ -90,6 +91,8 @@ def _load():
         "bca_batch_autotune": [P, i32, P],
         "bca_batch_set_shape": [P, i32, i32],
         "bca_batch_get_shape": [P, pi32, pi32],
+        "bca_batch_set_tracing": [i32],
+        "bca_batch_get_tracing": [pdbl, i32, ctypes.POINTER(i64)],
         "bca_server_create": [ctypes.c_size_t, i32, i32, P, ctypes.POINTER(P)],
         "bca_server_submit": [P, ctypes.POINTER(Params), P, P, ctypes.POINTER(ctypes.c_uint64)],
         "bca_server_poll": [P, ctypes.c_uint64, pi32],
@@ -356,6 +359,22 @@ def batch_solve(problems, stream=None):
 def batch_autotune(problems, stream=None):
     st = _current_stream() if stream is None else ctypes.c_void_p(stream)
     _check(_lib.bca_batch_autotune(_handles(problems), len(problems), st))
+
+
+BATCH_PHASES = ("prime", "rhs", "symv", "xupd", "stream", "global")
+
+
+def batch_set_tracing(on: bool):
+    """Phase tracing of the batched launches (bca_batch_set_tracing)."""
+    _check(_lib.bca_batch_set_tracing(1 if on else 0))
+
+
+def batch_get_tracing():
+    """Summed microseconds per batched phase kind, and the traced launch count."""
+    us = (ctypes.c_double * len(BATCH_PHASES))()
+    n = ctypes.c_int64()
+    _check(_lib.bca_batch_get_tracing(us, len(BATCH_PHASES), ctypes.byref(n)))
+    return dict(zip(BATCH_PHASES, list(us))), n.value
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = range(5)

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1331,6 +1332,14 @@ int set_problem_stream(bca_problem P, hipStream_t s) {
 namespace {
 
 std::mutex g_batch_mu;
+// phase tracing of the batched launches (bca_batch_set_tracing)
+struct BatchTrace {
+  std::atomic<bool> on{false};
+  std::mutex mu;
+  double us[BCA_BP_KINDS] = {0, 0, 0, 0, 0, 0};
+  int64_t launches = 0;
+};
+BatchTrace g_trace;
 struct BatchContext {
   void* buf = nullptr;   // descriptors + item lists + counters
   size_t cap = 0;
@@ -1452,7 +1461,7 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   int outer_max = 0, inner_max = 0;
   // Tile ranges of the symmetric products: kSymvTiles tiles of P_ij per item,
   // fixed by n_j alone so a problem is split the same way in every batch.
-  constexpr int kSymvTiles = 8;
+  constexpr int kSymvTiles = 2;
   for (int r = 0; r < count; ++r) {
     bca_problem P = probs[r];
     if (dev) {
@@ -1520,7 +1529,10 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   const size_t off_prime = off_stream + al(stream.size() * sizeof(BatchItem));
   const size_t off_cnt = off_prime + al(primei.size() * sizeof(BatchItem));
   const size_t n_cnt = (size_t)std::max(phases, 1) * kBatchCounterGroups + kBatchBarWords;
-  const size_t total = off_cnt + al(n_cnt * sizeof(unsigned int));
+  const bool tracing = g_trace.on.load() && !stream_only;
+  const size_t off_stamps = off_cnt + al(n_cnt * sizeof(unsigned int));
+  const size_t n_stamps = (size_t)std::max(phases, 1) + 1;   // the start and every barrier
+  const size_t total = off_stamps + (tracing ? al(n_stamps * sizeof(unsigned long long)) : 0);
   char* base = nullptr;
   if (dev) {
     if (total > cap)
@@ -1567,6 +1579,7 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   a.inner_max = inner_max;
   a.counters = reinterpret_cast<unsigned int*>(base + off_cnt);
   a.bar = a.counters + (size_t)std::max(phases, 1) * kBatchCounterGroups;
+  a.stamps = tracing ? reinterpret_cast<unsigned long long*>(base + off_stamps) : nullptr;
   a.stream_only = stream_only ? 1 : 0;
   const int grid = batch_grid_size();
   if (grid < 1) return fail(BCA_E_DEVICE, "batched kernel does not fit on this device");
@@ -1580,6 +1593,23 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   if (le != hipSuccess) return fail(BCA_E_DEVICE, "batched launch failed: %s", hipGetErrorString(le));
   if (ms) HIP_TRY(hipEventRecord(e1, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (tracing) {
+    // phase kinds between consecutive stamps: [prime], then per outer iteration
+    // inner_max x (RHS, SYMV, XUPD, STREAM) and the global step
+    std::vector<unsigned long long> st(n_stamps);
+    HIP_TRY(hipMemcpy(st.data(), a.stamps, n_stamps * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    std::vector<int> kind;
+    if (!primei.empty()) kind.push_back(BCA_BP_PRIME);
+    for (int o = 0; o < outer_max; ++o) {
+      for (int k = 0; k < inner_max; ++k)
+        for (int q : {BCA_BP_RHS, BCA_BP_SYMV, BCA_BP_XUPD, BCA_BP_STREAM}) kind.push_back(q);
+      kind.push_back(BCA_BP_GLOBAL);
+    }
+    std::lock_guard<std::mutex> lk(g_trace.mu);
+    for (size_t q = 0; q < kind.size() && q + 1 < st.size(); ++q)
+      g_trace.us[kind[q]] += (double)(st[q + 1] - st[q]) * 0.01;   // 100 MHz counter
+    g_trace.launches += 1;
+  }
   if (ms) {
     HIP_TRY(hipEventElapsedTime(ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -1666,6 +1696,24 @@ int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream) {
   return bca_batch_step(probs, count, most, hip_stream);
 }
 
+int bca_batch_set_tracing(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  if (on && !g_trace.on.load()) {
+    for (double& v : g_trace.us) v = 0.0;
+    g_trace.launches = 0;
+  }
+  g_trace.on = on != 0;
+  return BCA_OK;
+}
+
+int bca_batch_get_tracing(double* us, int32_t count, int64_t* launches) {
+  if (count < 0 || count > BCA_BP_KINDS || (count > 0 && !us)) return fail(BCA_E_INVALID, "bad tracing buffer");
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  for (int k = 0; k < count; ++k) us[k] = g_trace.us[k];
+  if (launches) *launches = g_trace.launches;
+  return BCA_OK;
+}
+
 int bca_batch_set_shape(bca_problem P, int32_t rows_per_tile, int32_t rows_per_item) {
   if (!P) return fail(BCA_E_INVALID, "null problem");
   if (rows_per_tile != 1 && rows_per_tile != 2 && rows_per_tile != 4 && rows_per_tile != 8)
@@ -1714,7 +1762,7 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
     buckets[b].push_back(P);
   }
   const int tiles[4] = {1, 2, 4, 8};
-  const int items[3] = {64, 256, 1024};
+  const int items[5] = {16, 32, 64, 256, 1024};
   for (size_t b = 0; b < buckets.size(); ++b) {
     auto& bp = buckets[b];
     for (auto P : bp) TRY(batch_check_basic(P));
@@ -1722,7 +1770,7 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
     int bt = 2, bi = 256;
     for (int ti = 0; ti < 4; ++ti) {
       if (batch_shape_code(bp[0]->nvec, tiles[ti]) < 0) continue;
-      for (int ii = 0; ii < 3; ++ii) {
+      for (int ii = 0; ii < 5; ++ii) {
         for (auto P : bp) {
           P->b_rows_tile = tiles[ti];
           P->b_rows_item = items[ii];

@@ -414,6 +414,8 @@ struct BatchArgs {
   unsigned int* counters;          // 8 work counters per phase (one per group of
                                    // workgroups), zeroed before the launch
   unsigned int* bar;               // grid barrier words (kBatchBarWords), zeroed before the launch
+  unsigned long long* stamps;      // phase tracing (or null): workgroup 0 stores the 100 MHz
+                                   // real-time counter at the start and after every grid barrier
   int stream_only;                 // 1: run only the prime phase (tile-shape timing)
 };
 constexpr int kBatchCounterGroups = 8;

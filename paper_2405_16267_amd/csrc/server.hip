@@ -81,7 +81,7 @@ size_t footprint(const bca_params& p, const std::vector<int64_t>& rows) {
   b += (size_t)N * M * nj * nj * 8 * 2;               // finalize work space (released after)
   int64_t mx = 0;
   for (auto r : rows) mx = std::max(mx, r);
-  b += (size_t)N * ((mx + 127) / 128) * 4 * ld * 8;             // batched partial sums
+  b += (size_t)N * ((mx + 15) / 16) * ld * 8;                   // batched partial sums (16-row items)
   b += (size_t)std::min<int64_t>(1024, N * ((mx + 3) / 4)) * ld * C * 8;   // one-problem partial sums
   return b + (1 << 20);
 }

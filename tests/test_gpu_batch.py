@@ -103,7 +103,7 @@ SHAPE_CASES = [(60, R) for R in (1, 2, 4, 8)] + [(120, R) for R in (1, 2, 4, 8)]
 
 def test_batch_every_tile_shape_against_oracle_f32():
     """One persistent launch over 18 FP32 instances (squared and logistic), each
-    forced onto its own tile shape and rows per item (64, 256, 1024 in turn), against
+    forced onto its own tile shape and rows per item (16, 32, 64, 256, 1024 in turn), against
     the FP64 oracle: z element-wise at 1e-5, the support where the oracle's top-kappa
     margin is clear of that, coefficients and objective at 1e-5 (reading R20)."""
     bca = _bca()
@@ -113,8 +113,8 @@ def test_batch_every_tile_shape_against_oracle_f32():
         m = 2400 + 131 * q
         w = datagen.batched_instance(40 + q, m, n, dtype="f32", max_iters=K)
         p = make(w)
-        p.set_batch_shape(R, (64, 256, 1024)[q % 3])
-        assert p.batch_shape() == (R, (64, 256, 1024)[q % 3])
+        p.set_batch_shape(R, (16, 32, 64, 256, 1024)[q % 5])
+        assert p.batch_shape() == (R, (16, 32, 64, 256, 1024)[q % 5])
         ws.append(w)
         P.append(p)
     bca.batch_step(P, K)
@@ -166,7 +166,7 @@ def test_batch_autotune_keeps_state_and_results():
     for p, zb in zip(P, z_before):
         assert np.array_equal(p.get_vector(bca.VEC_Z), zb)
         t, i = p.batch_shape()
-        assert t in (1, 2, 4, 8) and i in (64, 256, 1024)
+        assert t in (1, 2, 4, 8) and i in (16, 32, 64, 256, 1024)
     bca.batch_step(P, 3)
     bca.batch_step(Q, 3)
     for w, p, q in zip(ws, P, Q):

@@ -858,9 +858,9 @@ def exact_logistic_bench(args):
 
 
 # Offered rate of the serving trace, frozen: 1.5 x the plain method's rate on the
-# trace's first 20 requests, measured on one MI355X with the current kernels
-# (`--rate 0` measures it again and uses that instead).
-SERVE_PLAIN_RATE = 35.0
+# trace's first 20 requests, measured on one MI355X (32.9-33.6 solves/s over four
+# runs with the MFMA softmax kernels; `--rate 0` measures it again and uses that).
+SERVE_PLAIN_RATE = 33.3
 SERVE_RATE = 1.5 * SERVE_PLAIN_RATE
 
 

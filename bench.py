@@ -81,6 +81,12 @@ def workload(name):
         # the same shape, sparse SVM (hinge loss) on the sparse linear recipe's rows
         return datagen.svm_workload(1, N=8, m_per=50000, n=5000, kappa=50, k_true=50,
                                     n_blocks=4, dtype="f32", max_iters=100, name=name)
+    if name == "ssr_4x5000x1000x10_f32":
+        # the serving trace's softmax request: 4 partitions of 5,000 rows, n = 1,000,
+        # C = 10 classes, 30 nonzero rows of W*
+        w = datagen.softmax_request(4007, max_iters=100)
+        w.name = name
+        return w
     raise SystemExit("unknown workload " + name)
 
 
@@ -1086,11 +1092,11 @@ def main():
     t = time.perf_counter()
     w = workload(args.workload)
     log("generated %s in %.1f s" % (w.name, time.perf_counter() - t))
-    loss = {0: "squared", 1: "logistic", 3: "hinge"}[w.loss]
+    loss = {0: "squared", 1: "logistic", 2: "softmax", 3: "hinge"}[w.loss]
     total_iters = args.warmup + args.steps
     P = bca.Problem(loss, w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
                     rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
-                    max_iters=max(total_iters, 1), dtype=w.dtype)
+                    max_iters=max(total_iters, 1), dtype=w.dtype, n_classes=w.n_classes)
     t = time.perf_counter()
     for i in range(w.N):
         P.set_data(i, w.A[i], w.b[i])
@@ -1120,14 +1126,26 @@ def main():
     n_gl, gl_ms = P.timing(bca.KC_GLOBAL)
     pr, dr, br, it = P.residuals()
     log("residuals after %d iterations: p_r %.3e d_r %.3e b_r %.3e" % (it, pr, dr, br))
-    zr = np.sort(np.abs(P.get_vector(bca.VEC_Z)))[::-1]
+    zv = P.get_vector(bca.VEC_Z)
+    if w.n_classes > 1:   # row sparsity: the support is the rows of largest norm
+        zv = np.linalg.norm(zv.reshape(w.n, w.n_classes), axis=1)
+    zr = np.sort(np.abs(zv))[::-1]
     margin = float(zr[w.kappa - 1] - zr[w.kappa]) if w.kappa < w.n else float("inf")
 
     m_total = sum(w.rows)
     esize = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
-    # algorithmic bytes of one A-streaming pass: A once, plus b (read), nu (read and
-    # write) and omega-bar (write) per row
-    stream_bytes = m_total * w.n * esize + 32 * m_total
+    C = w.n_classes
+    if C == 1:
+        # algorithmic bytes of one A-streaming pass: A once, plus b (read), nu (read and
+        # write) and omega-bar (write) per row
+        stream_bytes = m_total * w.n * esize + 32 * m_total
+        stream_kernel = "stream_kernel"
+    else:
+        # the multi-class pass's three kernels: A twice (sample-space averages, then
+        # A^T E), the C-vector of averages written and read, omega-bar and nu read and
+        # written, e written and read, the labels read
+        stream_bytes = 2 * m_total * w.n * esize + 8 * 8 * C * m_total + 4 * m_total
+        stream_kernel = "dot_mfma_kernel+prox_mc_kernel+acc_mfma_kernel"
     stream_avg_s = st_ms / max(n_st, 1) / 1e3
     achieved = stream_bytes / stream_avg_s / 1e9
     bounds = [(w.n // w.n_blocks + (1 if j < w.n % w.n_blocks else 0)) for j in range(w.n_blocks)]
@@ -1136,7 +1154,7 @@ def main():
     inner_bytes = stream_bytes + factor_bytes
     ms_per_step = elapsed / args.steps * 1e3
     src_hash = source_hash(STREAM_SOURCES)
-    traffic, traffic_file = counter_traffic("stream_kernel", w.name, src_hash)
+    traffic, traffic_file = counter_traffic(stream_kernel, w.name, src_hash)
     gram_flops = sum(m * nj * (nj + 1) for m in w.rows for nj in bounds)
     gram_peak = {"f64": FP64_PEAK_TFLOPS, "f32": FP32_MFMA_PEAK_TFLOPS, "bf16": BF16_MFMA_PEAK_TFLOPS}[w.dtype]
     gram_tflops = gram_flops / (gram_ms / 1e3) / 1e12 if gram_ms > 0 else None
@@ -1159,7 +1177,7 @@ def main():
                    "rho_c": w.rho_c, "rho_b": w.rho_b, "rho_l": w.rho_l, "gamma": w.gamma},
         "inner_iters_per_s": args.steps * w.inner_iters / elapsed,
         "hbm_gbps_algorithmic": inner_bytes * w.inner_iters * args.steps / elapsed / 1e9,
-        "roofline": {"bound": "hbm", "kernel": "stream_kernel", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": stream_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "traffic_unit": "bytes per launch",
                      "traffic_source": traffic_file, "kernel_source": src_hash,

@@ -192,3 +192,39 @@ def test_batch_rejects_out_of_scope_problems():
         bca.batch_step([S], 1)
     assert e.value.code == -1
     S.close()
+
+
+def test_batch_phase_tracing_accounts_for_the_launch():
+    """Phase tracing (bca_batch_set_tracing): every phase kind of the launches made
+    while it is on is summed, the sums cover the launches' duration (one timestamp
+    per grid barrier; the host side of a launch is outside them), results are the
+    same bits as untraced launches, and turning tracing on again clears the sums."""
+    import time
+    bca = _bca()
+    ws = mix("f32", K=8)
+    P = [make(w) for w in ws]
+    Q = [make(w) for w in ws]
+    bca.batch_step(P, 1)
+    bca.batch_step(Q, 1)
+    bca.batch_set_tracing(True)
+    t = time.perf_counter()
+    bca.batch_step(P, 4)
+    wall_us = (time.perf_counter() - t) * 1e6
+    us, n = bca.batch_get_tracing()
+    bca.batch_set_tracing(False)
+    bca.batch_step(Q, 4)
+    assert n == 1
+    assert set(us) == set(bca.BATCH_PHASES)
+    for k in ("rhs", "symv", "xupd", "stream", "global"):
+        assert us[k] > 0.0, k
+    total = sum(us.values())
+    assert 0.2 * wall_us < total <= wall_us, (total, wall_us)
+    for p, q in zip(P, Q):
+        assert np.array_equal(p.get_vector(bca.VEC_Z), q.get_vector(bca.VEC_Z))
+    bca.batch_step(P, 1)             # untraced: the sums stay
+    assert bca.batch_get_tracing()[1] == 1
+    bca.batch_set_tracing(True)
+    assert bca.batch_get_tracing() == ({k: 0.0 for k in bca.BATCH_PHASES}, 0)
+    bca.batch_set_tracing(False)
+    for p in P + Q:
+        p.close()

@@ -70,6 +70,10 @@ def test_served_results_match_solo(dtype, tol):
     tickets = [submit(S, w) for w in ws]
     st = wait_all(S, tickets)
     assert all(s == bca.REQ_DONE for s in st), st
+    # the server's time report: the round activities ran, nothing is negative
+    tm = S.timing()
+    assert tm["batched"] > 0.0 and tm["softmax"] > 0.0 and tm["materialise"] > 0.0, tm
+    assert min(tm.values()) >= 0.0, tm
     checked = 0
     for w, t in zip(ws, tickets):
         idx, x, f, lat = S.fetch(t)

@@ -71,3 +71,56 @@ def test_config1_full_size_sampled_parity():
     gpr, gdr, gbr, _ = after["res"]
     assert abs(gpr - pr) <= 1e-9 * max(1.0, pr) and abs(gdr - dr) <= 1e-9 * max(1.0, dr)
     assert abs(gbr - br) <= 1e-9 * max(1.0, abs(br))
+
+
+def test_config1_full_size_last_iteration_and_support():
+    """The whole solve at full size (K = 100 outer iterations of the benchmark's
+    launch), checked at its last iteration: the oracle recomputes the 100th outer
+    iteration from the GPU's state after 99 -- the x-update of EVERY partition over
+    its 50,000 x 5,000 data (Algorithm 2, K_in inner iterations), then the global
+    step from those x_i -- and the GPU's x_i, z and support after 100 iterations are
+    compared with it (support where the top-kappa margin is clear of the FP32 error)."""
+    import paper_2405_16267_amd as bca
+    w = datagen.config1()
+    K = w.max_iters
+    P = bca.Problem("logistic", w.n, w.rows, w.n_blocks, w.kappa, gamma=w.gamma, rho_c=w.rho_c,
+                    rho_b=w.rho_b, rho_l=w.rho_l, inner_iters=w.inner_iters,
+                    max_iters=K, dtype="f32")
+    for i in range(w.N):
+        P.set_data(i, w.A[i], w.b[i])
+    P.finalize()
+    P.step(K - 1)
+    before = dict(x=[P.get_vector(bca.VEC_X, i) for i in range(w.N)],
+                  u=[P.get_vector(bca.VEC_U, i) for i in range(w.N)],
+                  om=[P.get_vector(bca.VEC_OMEGA, i) for i in range(w.N)],
+                  nu=[P.get_vector(bca.VEC_NU, i) for i in range(w.N)],
+                  z=P.get_vector(bca.VEC_Z), s=P.get_vector(bca.VEC_S), tv=P.get_vector(bca.VEC_TV))
+    P.step(1)
+    assert P.residuals()[3] == K
+    after = dict(x=[P.get_vector(bca.VEC_X, i) for i in range(w.N)], z=P.get_vector(bca.VEC_Z),
+                 support=P.support())
+    P.close()
+
+    xs = []
+    for i in range(w.N):
+        o = oracle.BiCADMM([datagen.widen(w.A[i])], [w.b[i]], w.loss, w.n_blocks, w.kappa, w.gamma,
+                           w.rho_c, w.rho_b, w.rho_l, n_partitions=w.N)
+        st = o.zero_state()
+        st.x[0] = before["x"][i]
+        st.u = np.array(before["u"])
+        st.u[0] = before["u"][i]     # this oracle holds partition i as its partition 0
+        st.z = before["z"]
+        st.omega[0] = before["om"][i]
+        st.nu[0] = before["nu"][i]
+        o.x_update(0, w.inner_iters, st)
+        assert rel(after["x"][i], st.x[0]) < 1e-5, i
+        xs.append(st.x[0].copy())
+    st.x = np.array(xs)
+    st.u = np.array(before["u"])
+    st.z = before["z"]
+    st.s = before["s"]
+    st.t, st.v = before["tv"]
+    o.global_update(st)
+    assert rel(after["z"], st.z) < 1e-5
+    assert o.topk_margin(st) > 1e-4 * float(np.max(np.abs(st.z)))
+    assert np.array_equal(after["support"], o.support(st))

@@ -320,8 +320,13 @@ int bca_batch_get_shape(bca_problem p, int32_t* rows_per_tile, int32_t* rows_per
 enum { BCA_REQ_QUEUED = 0, BCA_REQ_RUNNING = 1, BCA_REQ_DONE = 2, BCA_REQ_FAILED = 3,
        BCA_REQ_CANCELLED = 4 };
 
-/* Start a server (its scheduler thread) on hip_stream.
- * Errors: BCA_E_INVALID (max_slots < 1, round_iters < 1, zero budget). */
+/* Start a server (its scheduler and materialiser threads) whose rounds run on
+ * hip_stream; the server creates three more non-blocking streams of its own (two
+ * for softmax requests, one for materialising).  The batched launch of a round
+ * runs alone on the GPU (a cooperative launch that fills every CU), so the
+ * caller should not run other kernels on the device while the server is busy.
+ * Errors: BCA_E_INVALID (max_slots < 1, round_iters < 1, zero budget),
+ * BCA_E_DEVICE (no current device, or a stream could not be created). */
 int bca_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t round_iters, void* hip_stream,
                       bca_server* out);
 

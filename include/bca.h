@@ -242,8 +242,12 @@ const char* bca_last_error(void);
  * the global step of Algorithm 1, exactly as bca_step computes it (to rounding:
  * the batched streaming pass sums in a different order).  A problem's results do
  * not depend on which other problems share the batch.  Limits: one-class losses
- * (squared, logistic), FP32 or FP64 storage, n_j <= 1024, n <= 2048 (FP32) or
- * 1024 (FP64).  The call synchronises hip_stream.
+ * (squared, logistic, hinge), FP32 or FP64 storage, n_j <= 1024, n <= 2048 (FP32)
+ * or 1024 (FP64).  The launch is cooperative, with a grid that fills every CU, and
+ * its grid barriers need all of its workgroups resident: kernels that other
+ * streams run at the same time can stall it (a server whose materialiser ran
+ * kernels beside it made no progress for minutes), so run nothing else on the
+ * device during the call.  The call synchronises hip_stream.
  * Errors: BCA_E_INVALID (a problem outside the limits), BCA_E_STATE (not
  * finalized), BCA_E_NONFINITE, BCA_E_DEVICE. */
 

@@ -31,17 +31,26 @@ __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const
   const int lane = threadIdx.x & 63;
   const int a = lane >> 3, b = lane & 7;
   const bool diag = I == J;
+  // rows of the block's last tile row past n_j are zero in the stored tile: their
+  // 16-row bands (loads q) are not read
+  const int rows = I == T - 1 ? nj - PT * I : PT;
   symv_d2 p[4][8];
   const symv_d2* tp = reinterpret_cast<const symv_d2*>(tile) + lane;
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
+    if (16 * q < rows) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if constexpr (NTL)
-        p[q][k] = __builtin_nontemporal_load(tp + (q * 8 + k) * 64);
-      else
-        p[q][k] = tp[(q * 8 + k) * 64];
+      for (int k = 0; k < 8; ++k) {
+        if constexpr (NTL)
+          p[q][k] = __builtin_nontemporal_load(tp + (q * 8 + k) * 64);
+        else
+          p[q][k] = tp[(q * 8 + k) * 64];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p[q][k] = symv_d2{0.0, 0.0};
     }
+  }
   const int colJ = PT * J + 8 * b, rowI = PT * I + 2 * a;
   if (ce < 0) ce = C;
   for (int c = cb; c < ce; ++c) {

@@ -123,7 +123,6 @@ struct bca_server_s {
   std::vector<Request*> ready;     // materialised, joining at the next round
   std::vector<Request*> active;    // resident
   std::map<uint64_t, std::unique_ptr<Request>> all;
-  std::map<int64_t, std::pair<int, int>> shapes;   // tuned batched tile shapes (materialiser only)
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker, mat_worker;
@@ -191,9 +190,12 @@ int materialise(bca_server_s* S, Request* r) {
   {
     GpuTurn g(S, BCA_SRV_MAT_WAIT);
     rc = bca_finalize(r->prob);
-    // one-class requests: the batched pass's tile shape, tuned once per class of
-    // requests (storage type, 16-byte chunks per row rounded to a power of two,
-    // log2 of the tallest partition: the autotuner's own grouping) and reused
+    // one-class requests: the batched pass's tile shape, a fixed function of the
+    // request's shape (a timed choice would make its rounding depend on timing
+    // noise, so that the same request could give other bits on another server):
+    // the most rows per tile the row length allows (R x chunks per lane <= 8), 64
+    // rows per work item, 256 for rows of one 16-byte chunk per lane in tall
+    // partitions (such items are small, and each costs a call)
     if (rc == BCA_OK && p.loss != BCA_LOSS_SOFTMAX) {
       const int vec = p.a_dtype == BCA_F64 ? 2 : (p.a_dtype == BCA_F32 ? 4 : 8);
       const int nvec = (p.n_features + vec - 1) / vec;
@@ -201,18 +203,9 @@ int materialise(bca_server_s* S, Request* r) {
       while (nc < 8 && 64 * nc < nvec) nc *= 2;
       int64_t mx = 0;
       for (int i = 0; i < p.n_partitions; ++i) mx = std::max<int64_t>(mx, p.rows[i]);
-      int lg = 0;
-      while ((int64_t(1) << (lg + 1)) <= mx) ++lg;
-      const int64_t key = ((int64_t)p.a_dtype << 32) | ((int64_t)nc << 16) | lg;
-      auto it = S->shapes.find(key);
-      if (it != S->shapes.end()) {
-        rc = bca_batch_set_shape(r->prob, it->second.first, it->second.second);
-      } else {
-        rc = bca_batch_autotune(&r->prob, 1, S->mstream);
-        int rt = 0, ri = 0;
-        if (rc == BCA_OK) rc = bca_batch_get_shape(r->prob, &rt, &ri);
-        if (rc == BCA_OK) S->shapes[key] = {rt, ri};
-      }
+      const int rt = 8 / nc;
+      const int ri = (nc == 1 && mx >= 4096) ? 256 : 64;
+      rc = bca_batch_set_shape(r->prob, rt, ri);
     }
   }
   if (rc != BCA_OK) return rc;

@@ -31,14 +31,16 @@ __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const
   const int lane = threadIdx.x & 63;
   const int a = lane >> 3, b = lane & 7;
   const bool diag = I == J;
-  // rows of the block's last tile row past n_j are zero in the stored tile: their
-  // 16-row bands (loads q) are not read
+  // rows and columns past n_j (the block's last tile row and column) are zero in
+  // the stored tile: their 16-row bands (loads q) and this lane's 8 columns are
+  // not read when they lie wholly past it
   const int rows = I == T - 1 ? nj - PT * I : PT;
+  const bool cols = 8 * b < (J == T - 1 ? nj - PT * J : PT);
   symv_d2 p[4][8];
   const symv_d2* tp = reinterpret_cast<const symv_d2*>(tile) + lane;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (16 * q < rows) {
+    if (16 * q < rows && cols) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         if constexpr (NTL)

@@ -148,10 +148,11 @@ int bca_set_data(bca_problem p, int32_t part, const void* A, int64_t ld, const v
  * applies as one symmetric matrix-vector product.  With BCA_FLAG_EXACT_X the same
  * is done once per partition for H_i = 2 A_i^T A_i + (1/(N gamma) + rho_c) I
  * (squared loss) or the preconditioner A_i^T A_i / 4 + (1/(N gamma) + rho_c) I
- * (logistic loss); with
- * BCA_FLAG_WOODBURY for S_ij = rho_l A_ij A_ij^T + (1/(N gamma) + rho_c) I.  Also
- * allocates the batched form's partial sums for problems within its limits.
- * Resets the ADMM state to zero.
+ * (logistic loss); with BCA_FLAG_WOODBURY for S_ij = rho_l A_ij A_ij^T +
+ * (1/(N gamma) + rho_c) I.  Also allocates the batched form's partial sums for
+ * problems within its limits.  The Gram and factor work space comes from the
+ * stream-ordered allocator on the problem's stream (hipMallocAsync) and is
+ * released before the call returns.  Resets the ADMM state to zero.
  * Errors: BCA_E_STATE (a partition was never loaded), BCA_E_NONFINITE (K_ij not
  * positive definite in FP64), BCA_E_DEVICE. */
 int bca_finalize(bca_problem p);

@@ -317,15 +317,15 @@ int bca_batch_get_shape(bca_problem p, int32_t* rows_per_tile, int32_t* rows_per
  * keep running; the scheduler advances all resident requests together in rounds
  * of round_iters outer iterations (one-class requests in one batched persistent
  * launch, softmax requests with their own kernels on two streams of the server);
- * finished requests are retired between rounds, freeing their slot and memory for
- * waiting ones.  A request's result does not depend on the other requests it
+ * finished requests are retired between rounds, freeing their slot at once and
+ * their memory (for waiting ones) when a releaser thread has freed it.  A request's result does not depend on the other requests it
  * shares rounds with.  Submit/poll/fetch/cancel/stats are thread-safe. */
 
 /* Request states reported by bca_server_poll. */
 enum { BCA_REQ_QUEUED = 0, BCA_REQ_RUNNING = 1, BCA_REQ_DONE = 2, BCA_REQ_FAILED = 3,
        BCA_REQ_CANCELLED = 4 };
 
-/* Start a server (its scheduler and materialiser threads) whose rounds run on
+/* Start a server (its scheduler, materialiser and releaser threads) whose rounds run on
  * hip_stream; the server creates three more non-blocking streams of its own (two
  * for softmax requests, one for materialising).  The batched launch of a round
  * runs alone on the GPU (a cooperative launch that fills every CU), so the
@@ -363,11 +363,13 @@ int bca_server_stats(bca_server s, int32_t* queued, int32_t* running, double* us
 
 /* Wall-clock seconds the server's threads have spent so far, per activity, into
  * seconds[0 .. count-1] (count <= BCA_SRV_TIMES): the rounds' softmax work (issue
- * and wait), their batched launches, retiring finished requests, materialising
- * admitted ones, the materialiser waiting for a batched launch to end, and the
- * scheduler waiting for a materialiser call to end.  Errors: BCA_E_INVALID. */
+ * and wait), their batched launches, retiring finished requests (copying their
+ * results out), materialising admitted ones, the materialiser waiting for a
+ * batched launch to end, the scheduler waiting for a materialiser call to end, and
+ * the releaser freeing retired requests' memory (which waits for the device).
+ * Errors: BCA_E_INVALID. */
 enum { BCA_SRV_SOFTMAX = 0, BCA_SRV_BATCHED = 1, BCA_SRV_RETIRE = 2, BCA_SRV_MATERIALISE = 3,
-       BCA_SRV_MAT_WAIT = 4, BCA_SRV_SCHED_WAIT = 5, BCA_SRV_TIMES = 6 };
+       BCA_SRV_MAT_WAIT = 4, BCA_SRV_SCHED_WAIT = 5, BCA_SRV_RELEASE = 6, BCA_SRV_TIMES = 7 };
 int bca_server_timing(bca_server s, double* seconds, int32_t count);
 
 /* Stop the scheduler and release every resident request. */

@@ -437,10 +437,10 @@ class Server:
 
     def timing(self):
         """Seconds per server activity (bca_server_timing)."""
-        t = (ctypes.c_double * 6)()
-        _check(_lib.bca_server_timing(self._h, t, 6))
+        t = (ctypes.c_double * 7)()
+        _check(_lib.bca_server_timing(self._h, t, 7))
         return dict(zip(("softmax", "batched", "retire", "materialise", "materialiser_wait",
-                         "scheduler_wait"), list(t)))
+                         "scheduler_wait", "release"), list(t)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

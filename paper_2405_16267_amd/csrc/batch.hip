@@ -69,30 +69,76 @@ int batch_shape_code(int nvec, int R) {
   return -1;
 }
 
+// Item functions are called out of line, so their pointer arguments are generic:
+// loads through them become FLAT instructions, which count on both the vector
+// memory and the LDS counters, and waiting for one of them means waiting for all
+// (lgkmcnt(0)).  The streaming item therefore casts its pointers to the global
+// (and its LDS scratch to the local) address space, and copies the problem's
+// fields to registers first: its own stores of omega-bar and nu could otherwise
+// alias the BatchInst and make the compiler re-read those fields, with a wait for
+// every load in flight, on each tile.
+template <typename P>
+using gptr = __attribute__((address_space(1))) P*;
+template <typename P>
+__device__ __forceinline__ gptr<P> glob(P* p) {
+  return (gptr<P>)p;
+}
+typedef __attribute__((address_space(3))) double* lds_dptr;
+
+template <typename V>
+__device__ __forceinline__ V load_nt(gptr<const V> p) {
+  static_assert(sizeof(V) == 16, "16-byte vectors only");
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 t = __builtin_nontemporal_load((gptr<const u32x4>)p);
+  V v;
+  __builtin_memcpy(&v, &t, 16);
+  return v;
+}
+
+// Tiles kept in flight per wavefront: a ring of D tile buffers, the load of tile
+// t + D issued as soon as tile t is processed, so that D tiles (about 4 KB to
+// 16 KB per wavefront) are in flight while one is processed; D shrinks as the tile
+// grows to bound the registers (D R NC <= 16 chunks of 16 bytes per lane).
+constexpr int stream_depth(int R, int NC) { return R * NC <= 2 ? 4 : (R * NC <= 4 ? 3 : 2); }
+
 // LG: the widest FP32 shape (32 columns per lane) keeps its FP64 partial sums of
 // A^T e in LDS (lg, 32 x BT doubles) instead of 64 registers, which would
 // otherwise set the register budget of the whole persistent kernel.
 template <typename T, int NC, int R, int S>
-__device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk, int mode, double* lg) {
+__device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk, int mode, double* lg_) {
   using TR = Traits<T>;
   using V = typename TR::vec_t;
   using acc = typename TR::acc_t;
   constexpr int VEC = TR::VEC;
   constexpr bool LG = NC * VEC == 32;
   constexpr int LSEG = 64 / S;  // lanes per segment
+  constexpr int D = stream_depth(R, NC);
+  const lds_dptr lg = (lds_dptr)lg_;
   const int lane = threadIdx.x & 63;
   const int sl = lane % LSEG, seg = lane / LSEG;
+  // the problem's fields, read once
+  const int64_t ld = I.ld;
+  const int nvec = I.nvec;
   const int64_t r0 = I.row_off[part];
   const int64_t m = I.row_off[part + 1] - r0;
-  const int64_t lo = (int64_t)chunk * I.rows_per_item;
-  const int64_t hi = lo + I.rows_per_item < m ? lo + I.rows_per_item : m;
-  const acc* xs = reinterpret_cast<const acc*>(I.xs) + (int64_t)part * I.ld;
+  const int64_t rows_per_item = I.rows_per_item;
+  const int items_per_part = I.items_per_part;
+  const int loss = I.loss, M = I.M;
+  const double rho_l = I.rho_l, inv_M = I.inv_M;
+  const gptr<const double> bv = glob(I.b);
+  const gptr<double> omv = glob(I.omega);
+  const gptr<double> nuv = glob(I.nu);
+  const gptr<const T> Ab = glob(reinterpret_cast<const T*>(I.A)) + r0 * ld;
+  const gptr<const acc> xs = glob(reinterpret_cast<const acc*>(I.xs)) + (int64_t)part * ld;
+  const gptr<double> gp = glob(I.gpart) + ((int64_t)part * items_per_part + chunk) * ld;
+  const int64_t lo = (int64_t)chunk * rows_per_item;
+  const int64_t hi = lo + rows_per_item < m ? lo + rows_per_item : m;
   acc xr[NC][VEC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const int k = sl + LSEG * q;
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) xr[q][e] = k < I.nvec ? xs[k * VEC + e] : acc(0);
+    for (int e = 0; e < VEC; ++e) xr[q][e] = k < nvec ? xs[k * VEC + e] : acc(0);
   }
   double g[LG ? 1 : NC][LG ? 1 : VEC];
 #pragma unroll
@@ -104,55 +150,44 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
       else
         g[q][e] = 0.0;
     }
-  const T* Ab = reinterpret_cast<const T*>(I.A) + r0 * I.ld;
   // Branch-free loads (rows past the item's end re-read its last row, chunks past
-  // the row's end its last chunk: x is zero there and e is zero on such rows), and
-  // the wave's next tile is loaded before the current one is processed.
-  int kc[NC];
+  // the row's end its last chunk: x is zero there and e is zero on such rows).
+  // byte offsets of the lane's chunks in a row
+  uint32_t kb[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) kc[q] = min(sl + LSEG * q, I.nvec - 1);
-  // a wave tile is S R rows: segment s takes rows rt + s R .. rt + s R + R - 1
+  for (int q = 0; q < NC; ++q) kb[q] = 16u * (uint32_t)min(sl + LSEG * q, nvec - 1);
+  // a wave tile is S R rows: segment s takes rows rt + s R .. rt + s R + R - 1; with
+  // one segment the row is the same for the whole wavefront, and its address is
+  // kept in scalar registers (a 64-bit address per lane and chunk would take 2 NC
+  // vector registers per row in flight)
   auto load_tile = [&](V (&dst)[R][NC], int64_t t0) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t row = min(t0 + seg * R + r, hi - 1);
-      const V* rp = reinterpret_cast<const V*>(Ab + row * I.ld);
+      uint64_t base = (uint64_t)(Ab + row * ld);
+      if constexpr (S == 1)
+        base = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) dst[r][q] = load_stream(rp + kc[q]);
+      for (int q = 0; q < NC; ++q) dst[r][q] = load_nt<V>((gptr<const V>)(base + kb[q]));
     }
   };
   // Per-row values (b, omega-bar, nu) of a tile are loaded together with its A
-  // rows: loads complete in issue order, so a row value loaded after the next
-  // tile's prefetch would make the wavefront wait for that whole prefetch.
+  // rows: loads complete in issue order, so a row value loaded after later tiles'
+  // loads would make the wavefront wait for those too.  The rows of a tile lie
+  // beyond those of every earlier tile, so reading their omega-bar and nu before
+  // the earlier tiles' stores is safe.
   struct RowVals {
     double b, om, nu;
   };
   auto load_rows = [&](int64_t t0) {
-    RowVals rv{0.0, 0.0, 0.0};
-    if (sl < R) {
-      const int64_t gr = r0 + min(t0 + seg * R + sl, hi - 1);
-      rv.b = I.b[gr];
-      rv.om = I.omega[gr];
-      rv.nu = I.nu[gr];
-    }
-    return rv;
+    // lanes past the segment's R rows read its last row (one address, unused)
+    const int64_t gr = r0 + min(t0 + seg * R + min(sl, R - 1), hi - 1);
+    return RowVals{bv[gr], omv[gr], nuv[gr]};
   };
-  constexpr int64_t STEP = (int64_t)S * R;
-  V v[R][NC];
-  RowVals rv{0.0, 0.0, 0.0};
-  if (lo < hi) {
-    load_tile(v, lo);
-    rv = load_rows(lo);
-  }
-  for (int64_t rt = lo; rt < hi; rt += STEP) {
-    // the next tile's loads go out before this tile's arithmetic; its rows lie
-    // beyond this tile's, so reading their omega-bar and nu here is safe
-    V vn[R][NC];
-    RowVals rvn{0.0, 0.0, 0.0};
-    if (rt + STEP < hi) {
-      load_tile(vn, rt + STEP);
-      rvn = load_rows(rt + STEP);
-    }
+  // One tile: row sums of A x, the omega-bar/nu step of its rows, and e times
+  // its rows added to the partial sums of A^T e.
+  auto process = [&](const V (&v)[R][NC], const RowVals& rv, int64_t rt) {
     double mine = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -174,14 +209,14 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
     const int64_t row = rt + seg * R + sl;
     if (sl < R && row < hi) {
       const int64_t gr = r0 + row;
-      const double av = mine * I.inv_M;
+      const double av = mine * inv_M;
       double nu = rv.nu;
       if (mode == 0) {
-        const double om = prox_scalar(I.loss, av + nu, rv.b, I.M, I.rho_l,
-                                      I.loss == BCA_LOSS_SQUARED ? 0.0 : rv.om);
+        const double om = prox_scalar(loss, av + nu, rv.b, M, rho_l,
+                                      loss == BCA_LOSS_SQUARED ? 0.0 : rv.om);
         nu = nu + av - om;
-        I.omega[gr] = om;
-        I.nu[gr] = nu;
+        omv[gr] = om;
+        nuv[gr] = nu;
         e = om - av - nu;
       } else {
         e = rv.om - av - nu;
@@ -208,11 +243,35 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
         else
           g[q][c] += (double)t;
       }
+  };
+  // The ring's loads are unconditional (tiles past the item's end re-read its last
+  // row, which the cache holds): a conditional load would make the compiler copy
+  // the buffers between iterations, and each copy waits for its load.
+  constexpr int64_t STEP = (int64_t)S * R;
+  const int64_t ntiles = lo < hi ? (hi - lo + STEP - 1) / STEP : 0;
+  if (ntiles > 0) {
+    V buf[D][R][NC];
+    RowVals rvb[D];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int d = 0; d < D; ++d) {
+      load_tile(buf[d], lo + d * STEP);
+      rvb[d] = load_rows(lo + d * STEP);
+    }
+    int64_t t = 0;
+    for (; t + D <= ntiles; t += D) {
 #pragma unroll
-      for (int q = 0; q < NC; ++q) v[r][q] = vn[r][q];
-    rv = rvn;
+      for (int d = 0; d < D; ++d) {
+        process(buf[d], rvb[d], lo + (t + d) * STEP);
+        // the buffer's next loads stay after its last use (else they need
+        // registers of their own)
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(buf[d], lo + (t + d + D) * STEP);
+        rvb[d] = load_rows(lo + (t + d + D) * STEP);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d)
+      if (t + d < ntiles) process(buf[d], rvb[d], lo + (t + d) * STEP);
   }
   // segments hold sums over different rows for the same columns: combine them
   if constexpr (S > 1 && !LG) {
@@ -223,12 +282,11 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
 #pragma unroll
         for (int o = LSEG; o < 64; o <<= 1) g[q][c] += __shfl_xor(g[q][c], o, 64);
   }
-  double* gp = I.gpart + ((int64_t)part * I.items_per_part + chunk) * I.ld;
   if (seg == 0) {
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int k = sl + LSEG * q;
-      if (k < I.nvec) {
+      if (k < nvec) {
 #pragma unroll
         for (int c = 0; c < VEC; ++c) {
           if constexpr (LG)

@@ -116,20 +116,22 @@ struct bca_server_s {
   std::mutex gpu_mu;               // the batched launch, or one materialiser call
   std::condition_variable cv;      // wakes the scheduler
   std::condition_variable mcv;     // wakes the materialiser
+  std::condition_variable rcv;     // wakes the releaser
   bool kick = false;               // something for the scheduler (submit, cancel, ready)
   std::deque<Request*> queue;      // submitted, not admitted
   std::deque<Request*> to_mat;     // admitted, waiting for the materialiser
   int materialising = 0;           // taken by the materialiser, not finished
   std::vector<Request*> ready;     // materialised, joining at the next round
+  std::deque<Request*> to_free;    // retired, device memory not yet released
   std::vector<Request*> active;    // resident
   std::map<uint64_t, std::unique_ptr<Request>> all;
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker, mat_worker;
+  std::thread worker, mat_worker, rel_worker;
   // statistics
   int64_t rounds = 0;
   double busy_s = 0;
-  double times[BCA_SRV_TIMES] = {0, 0, 0, 0, 0, 0};   // guarded by mu
+  double times[BCA_SRV_TIMES] = {};   // guarded by mu
 };
 
 namespace {
@@ -147,12 +149,14 @@ void release(Request* r) {
   r->b.shrink_to_fit();
 }
 
-// Final state of a request; with the server lock held.
-void settle(bca_server_s* S, Request* r, int state, const std::string& err) {
+// Final state of a request; with the server lock held.  `freed`: its device
+// memory is already released (else the materialiser releases it later and returns
+// its bytes to the budget then).
+void settle(bca_server_s* S, Request* r, int state, const std::string& err, bool freed = true) {
   r->state = state;
   r->err = err;
   r->t_done = now_s();
-  S->used -= r->bytes;
+  if (freed) S->used -= r->bytes;
 }
 
 // Create, load and finalize the resident problem of an admitted request on the
@@ -224,6 +228,33 @@ int collect(Request* r) {
   if (rc == BCA_OK) rc = bca_get_objective(r->prob, &r->objective);
   if (rc == BCA_OK) rc = bca_get_residuals(r->prob, nullptr, nullptr, nullptr, &r->iters);
   return rc;
+}
+
+// Releases retired requests (device memory and host copies).  bca_destroy waits
+// for the request's stream and hipFree for the whole device, i.e. for the round
+// running at the time: on a thread of its own that wait holds up neither the
+// scheduler nor the materialiser.  The bytes return to the budget once freed.
+void releaser(bca_server_s* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    Request* f = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->rcv.wait(lk, [&] { return S->stop || !S->to_free.empty(); });
+      if (S->stop) break;
+      f = S->to_free.front();
+      S->to_free.pop_front();
+    }
+    const double t = now_s();
+    release(f);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->used -= f->bytes;
+      S->times[BCA_SRV_RELEASE] += now_s() - t;
+      S->kick = true;   // room in the budget for waiting requests
+    }
+    S->cv.notify_all();
+  }
 }
 
 void materialiser(bca_server_s* S) {
@@ -362,16 +393,19 @@ void scheduler(bca_server_s* S) {
         continue;
       }
       gone.push_back(r);
-      release(r);
     }
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (size_t q = 0; q < gone.size(); ++q) settle(S, gone[q], outcome[q].first, outcome[q].second);
+      for (size_t q = 0; q < gone.size(); ++q) {
+        settle(S, gone[q], outcome[q].first, outcome[q].second, false);
+        S->to_free.push_back(gone[q]);
+      }
       S->active = keep;
       S->rounds += 1;
       S->busy_s += now_s() - t0;
       S->times[BCA_SRV_RETIRE] += now_s() - tm;
     }
+    if (!gone.empty()) S->rcv.notify_all();
     S->cv.notify_all();
   }
 }
@@ -402,6 +436,7 @@ int bca_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t round_
   }
   S->worker = std::thread(scheduler, S);
   S->mat_worker = std::thread(materialiser, S);
+  S->rel_worker = std::thread(releaser, S);
   *out = S;
   return BCA_OK;
 }
@@ -502,8 +537,10 @@ int bca_server_destroy(bca_server S) {
   }
   S->cv.notify_all();
   S->mcv.notify_all();
+  S->rcv.notify_all();
   if (S->worker.joinable()) S->worker.join();
   if (S->mat_worker.joinable()) S->mat_worker.join();
+  if (S->rel_worker.joinable()) S->rel_worker.join();
   for (auto& kv : S->all)
     if (kv.second->prob) bca_destroy(kv.second->prob);
   for (int q = 0; q < kSideStreams; ++q)

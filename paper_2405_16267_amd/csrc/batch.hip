@@ -329,27 +329,43 @@ __device__ __forceinline__ void stream_item_dispatch(const BatchInst& I, int par
 //   SYMV (partition, block, tile range): slots of y = P_ij r (symv_impl.h);
 //   XUPD (partition, block, 64-row slot row): x += y, y summed from the slots in a
 //        fixed order.
+// (Global-address-space pointers and fields read up front, as in the streaming
+// item: generic pointers would make every load a FLAT load.)
 __device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk, int cbeg) {
   const int c0 = I.col_off[blk];
   const int nj = I.col_off[blk + 1] - c0;
   const int c = cbeg + (threadIdx.x & 63);
   if (c >= nj) return;
   const int P = I.items_per_part;
+  const int64_t ld = I.ld;
   const int k = c0 + c;
-  const double* gb = I.gpart + (int64_t)part * P * I.ld + k;
-  // eight partial sums, so eight loads per lane are in flight
+  const int64_t o = (int64_t)part * I.n + k;
+  const double rho_l = I.rho_l, rho_c = I.rho_c, shift = I.shift;
+  const double zk = glob(I.z)[k], uo = glob(I.u)[o], xo = glob(I.x)[o];
+  const gptr<const double> gb = glob(I.gpart) + (int64_t)part * P * ld + k;
+  // eight partial sums (partial w goes to s[w mod 8], in increasing w); the loads
+  // of four groups of eight are issued before any is added
   double s[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) s[u] = 0.0;
   int w = 0;
-  for (; w + 8 <= P; w += 8) {
+  for (; w + 32 <= P; w += 32) {
+    double v[32];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += gb[(int64_t)(w + u) * I.ld];
+    for (int u = 0; u < 32; ++u) v[u] = gb[(int64_t)(w + u) * ld];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) s[u & 7] += v[u];
   }
-  for (; w < P; ++w) s[0] += gb[(int64_t)w * I.ld];
+  for (; w + 8 <= P; w += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = gb[(int64_t)(w + u) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += v[u];
+  }
+  for (; w < P; ++w) s[0] += gb[(int64_t)w * ld];
   const double ate = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  const int64_t o = (int64_t)part * I.n + k;
-  I.rhs[o] = I.rho_l * ate + I.rho_c * (I.z[k] - I.u[o]) - I.shift * I.x[o];
+  glob(I.rhs)[o] = rho_l * ate + rho_c * (zk - uo) - shift * xo;
 }
 
 // Tiles [t0, t1) of block (part, blk), one after the other, by one wavefront.
@@ -368,7 +384,10 @@ __device__ __forceinline__ void symv_item(const BatchInst& I, int part, int blk,
   }
 }
 
-// x += y over the 64 features of slot row R of block (part, blk).
+// x += y over the 64 features of slot row R of block (part, blk).  y is summed from
+// the row's T slots in the order of symv_gather (two alternating sums); the slots
+// are loaded together first (T <= 16 for the blocks of the batched form, n_j <=
+// 1024; larger T takes the rest one by one).
 __device__ __noinline__ void xupd_item(const BatchInst& I, int part, int blk, int R) {
   const int bid = part * I.M + blk;
   const int c0 = I.col_off[blk];
@@ -376,15 +395,43 @@ __device__ __noinline__ void xupd_item(const BatchInst& I, int part, int blk, in
   const int i = R * PT + (threadIdx.x & 63);
   if (i >= nj) return;
   const int T = (nj + PT - 1) / PT;
-  const double y = symv_gather(I.ypart + (int64_t)bid * I.tmax * I.tmax * PT, i, 0, 1, T);
   const int64_t o = (int64_t)part * I.n + c0 + i;
-  const double xn = I.x[o] + y;
-  I.x[o] = xn;
   const int64_t so = (int64_t)part * I.ld + c0 + i;
-  if (I.dtype == BCA_F64)
-    reinterpret_cast<double*>(I.xs)[so] = xn;
+  const bool f64 = I.dtype == BCA_F64;
+  const gptr<double> xv = glob(I.x);
+  const gptr<void> xs = glob(I.xs);
+  const gptr<const double> p =
+      glob(I.ypart) + (int64_t)bid * I.tmax * I.tmax * PT + ((int64_t)(i >> 6) * T * PT + (i & 63));
+  const double xo = xv[o];
+  constexpr int TU = 16;
+  double v[TU];
+#pragma unroll
+  for (int S = 0; S < TU; ++S)
+    if (S < T) v[S] = p[(int64_t)S * PT];
+  double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+  for (int S = 0; S < TU; S += 2) {
+    if (S + 2 <= T) {
+      y0 += v[S];
+      y1 += v[S + 1];
+    } else if (S + 1 == T) {
+      y0 += v[S];
+    }
+  }
+  if (T > TU) {
+    int S = TU;
+    for (; S + 2 <= T; S += 2) {
+      y0 += p[(int64_t)S * PT];
+      y1 += p[(int64_t)(S + 1) * PT];
+    }
+    if (S < T) y0 += p[(int64_t)S * PT];
+  }
+  const double xn = xo + (y0 + y1);
+  xv[o] = xn;
+  if (f64)
+    ((gptr<double>)xs)[so] = xn;
   else
-    reinterpret_cast<float*>(I.xs)[so] = (float)xn;
+    ((gptr<float>)xs)[so] = (float)xn;
 }
 
 // Out of line, with 7 multisection points per round, so that the global step's

@@ -95,6 +95,71 @@ __device__ __forceinline__ V load_nt(gptr<const V> p) {
   return v;
 }
 
+// Lane exchanges of gfx950: after swap32(a, b) lanes 32-63 of a and lanes 0-31 of
+// b have traded places; after swap16(a, b) the odd 16-lane rows of a and the even
+// rows of b have.  In both, a + b is then, in every lane, the lane's own value of
+// one of the pair plus its partner's (lane ^ 32, lane ^ 16) value of the same one:
+// of a where the lane's bit (5, 4) is clear, of b where it is set.
+__device__ __forceinline__ void swap32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Sums over the wavefront of R (2, 4, 8) per-lane values at once (reduce-scatter):
+// each halving step over lane bit 5, 4, 3 adds half of the remaining values to the
+// partner lane's and keeps the upper half where the lane's bit is set, so that
+// after log2 R steps the lane holds a partial of row lane >> (6 - log2 R); the
+// remaining low bits are summed as in wave_sum_dpp.  Every lane of a group of
+// 64 / R returns its row's total: about 40 instructions for 8 rows where 8 full
+// wave sums take about 240.
+template <int R>
+__device__ __forceinline__ double rows_sum_scatter(double (&v)[R]) {
+  constexpr int K = R == 2 ? 1 : (R == 4 ? 2 : 3);
+  static_assert(R == 2 || R == 4 || R == 8, "2, 4 or 8 rows");
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int half = R >> (i + 1);
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      double a = v[j], b = v[j + half];
+      if (i == 0) {
+        swap32(a, b);
+        v[j] = a + b;
+      } else if (i == 1) {
+        swap16(a, b);
+        v[j] = a + b;
+      } else {
+        const double pa = dpp_f64<0x128>(a), pb = dpp_f64<0x128>(b);   // lane ^ 8
+        v[j] = (lane & 8) ? b + pb : a + pa;
+      }
+    }
+  }
+  double x = v[0];
+  x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141>(x);   // row_half_mirror
+  if constexpr (K <= 2) x += dpp_f64<0x140>(x);   // row_mirror
+  if constexpr (K <= 1) {
+    double t = x;
+    swap16(x, t);
+    x = x + t;
+  }
+  return x;
+}
+
 // Tiles kept in flight per wavefront: a ring of D tile buffers, the load of tile
 // t + D issued as soon as tile t is processed, so that D tiles (about 4 KB to
 // 16 KB per wavefront) are in flight while one is processed; D shrinks as the tile
@@ -116,6 +181,14 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
   const lds_dptr lg = (lds_dptr)lg_;
   const int lane = threadIdx.x & 63;
   const int sl = lane % LSEG, seg = lane / LSEG;
+  // One-segment tiles of several rows reduce their row sums together
+  // (rows_sum_scatter): row r's total is then in lanes r G .. r G + G - 1 (G =
+  // 64 / R), and lane r G runs the row's prox; otherwise lane sl < R of the
+  // segment runs row sl's.
+  constexpr bool RS = S == 1 && R > 1;
+  constexpr int G = 64 / R;
+  const int myrow = RS ? lane / G : sl;              // the row this lane's values are for
+  const bool leader = RS ? (lane % G) == 0 : sl < R;
   // the problem's fields, read once
   const int64_t ld = I.ld;
   const int nvec = I.nvec;
@@ -182,32 +255,46 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
   };
   auto load_rows = [&](int64_t t0) {
     // lanes past the segment's R rows read its last row (one address, unused)
-    const int64_t gr = r0 + min(t0 + seg * R + min(sl, R - 1), hi - 1);
+    const int64_t gr = r0 + min(t0 + seg * R + min(myrow, R - 1), hi - 1);
     return RowVals{bv[gr], omv[gr], nuv[gr]};
   };
   // One tile: row sums of A x, the omega-bar/nu step of its rows, and e times
   // its rows added to the partial sums of A^T e.
   auto process = [&](const V (&v)[R][NC], const RowVals& rv, int64_t rt) {
     double mine = 0.0;
+    if constexpr (RS) {
+      double dv[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      acc d = acc(0);
+      for (int r = 0; r < R; ++r) {
+        acc d = acc(0);
 #pragma unroll
-      for (int q = 0; q < NC; ++q)
+        for (int q = 0; q < NC; ++q)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) d += vget(v[r][q], e) * xr[q][e];
-      double sv = (double)d;
-      if constexpr (S == 1) {
-        sv = wave_sum_dpp(sv);
-      } else {
-        sv = row16_sum_dpp(sv);                          // 16-lane segments
-        if constexpr (S == 2) sv += __shfl_xor(sv, 16, 64);  // 32-lane segments
+          for (int e = 0; e < VEC; ++e) d += vget(v[r][q], e) * xr[q][e];
+        dv[r] = (double)d;
       }
-      if (sl == r) mine = sv;
+      mine = rows_sum_scatter<R>(dv);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc d = acc(0);
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) d += vget(v[r][q], e) * xr[q][e];
+        double sv = (double)d;
+        if constexpr (S == 1) {
+          sv = wave_sum_dpp(sv);
+        } else {
+          sv = row16_sum_dpp(sv);                          // 16-lane segments
+          if constexpr (S == 2) sv += __shfl_xor(sv, 16, 64);  // 32-lane segments
+        }
+        if (sl == r) mine = sv;
+      }
     }
     double e = 0.0;
-    const int64_t row = rt + seg * R + sl;
-    if (sl < R && row < hi) {
+    const int64_t row = rt + seg * R + myrow;
+    if (leader && row < hi) {
       const int64_t gr = r0 + row;
       const double av = mine * inv_M;
       double nu = rv.nu;
@@ -226,8 +313,8 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (S == 1)
-        er[r] = (acc)__hiloint2double(__builtin_amdgcn_readlane(__double2hiint(e), r),
-                                      __builtin_amdgcn_readlane(__double2loint(e), r));
+        er[r] = (acc)__hiloint2double(__builtin_amdgcn_readlane(__double2hiint(e), RS ? r * G : r),
+                                      __builtin_amdgcn_readlane(__double2loint(e), RS ? r * G : r));
       else
         er[r] = (acc)__shfl(e, seg * LSEG + r, 64);
     }

@@ -325,8 +325,9 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
         acc t = acc(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) t += er[r] * vget(v[r][q], c);
-        if constexpr (LG)
-          lg[(q * VEC + c) * BT + threadIdx.x] += (double)t;
+        if constexpr (LG)   // an LDS add (the slot is this lane's own): no read back
+          __hip_atomic_fetch_add(&lg[(q * VEC + c) * BT + threadIdx.x], (double)t, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
         else
           g[q][c] += (double)t;
       }

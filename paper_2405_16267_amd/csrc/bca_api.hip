@@ -1768,6 +1768,7 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
     for (auto P : bp) TRY(batch_check_basic(P));
     float best = 1e30f;
     int bt = 2, bi = 256;
+    std::vector<std::tuple<float, int, int>> timed;   // (ms, rows per tile, rows per item)
     for (int ti = 0; ti < 4; ++ti) {
       if (batch_shape_code(bp[0]->nvec, tiles[ti]) < 0) continue;
       for (int ii = 0; ii < 5; ++ii) {
@@ -1784,6 +1785,7 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
           TRY(batch_launch(bp.data(), (int)bp.size(), outer, s, true, &ms));
           ms2 = std::min(ms2, ms);
         }
+        timed.emplace_back(ms2, tiles[ti], items[ii]);
         if (ms2 < best) {
           best = ms2;
           bt = tiles[ti];
@@ -1791,6 +1793,15 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
         }
       }
     }
+    // Among the shapes within 3 % of the fastest, the one with the most rows per
+    // item: fewer items leave fewer partial sums for the RHS phase to reduce (not
+    // part of the timed pass), and a group timed alone favours small items that
+    // spread it over the idle GPU, which a full batch does not need.
+    for (const auto& c : timed)
+      if (std::get<0>(c) <= 1.03f * best && std::get<2>(c) > bi) {
+        bt = std::get<1>(c);
+        bi = std::get<2>(c);
+      }
     for (auto P : bp) {
       P->b_rows_tile = bt;
       P->b_rows_item = bi;

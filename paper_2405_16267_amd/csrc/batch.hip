@@ -417,43 +417,135 @@ __device__ __forceinline__ void stream_item_dispatch(const BatchInst& I, int par
 //   SYMV (partition, block, tile range): slots of y = P_ij r (symv_impl.h);
 //   XUPD (partition, block, 64-row slot row): x += y, y summed from the slots in a
 //        fixed order.
-// (Global-address-space pointers and fields read up front, as in the streaming
-// item: generic pointers would make every load a FLAT load.)
-__device__ __noinline__ void rhs_item(const BatchInst& I, int part, int blk, int cbeg) {
-  const int c0 = I.col_off[blk];
-  const int nj = I.col_off[blk + 1] - c0;
-  const int c = cbeg + (threadIdx.x & 63);
-  if (c >= nj) return;
-  const int P = I.items_per_part;
-  const int64_t ld = I.ld;
-  const int k = c0 + c;
-  const int64_t o = (int64_t)part * I.n + k;
-  const double rho_l = I.rho_l, rho_c = I.rho_c, shift = I.shift;
-  const double zk = glob(I.z)[k], uo = glob(I.u)[o], xo = glob(I.x)[o];
-  const gptr<const double> gb = glob(I.gpart) + (int64_t)part * P * ld + k;
-  // eight partial sums (partial w goes to s[w mod 8], in increasing w); the loads
-  // of four groups of eight are issued before any is added
-  double s[8];
+// Wave-uniform values read from memory stay in vector registers unless the
+// compiler is told they are uniform: these move them to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+}
+__device__ __forceinline__ double uni(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+template <typename P>
+__device__ __forceinline__ gptr<P> uni(gptr<P> p) {
+  return (gptr<P>)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+template <typename P>
+__device__ __forceinline__ gptr<P> uni_glob(P* p) {
+  return uni(glob(p));
+}
+__device__ __forceinline__ BatchItem load_item(gptr<const BatchItem> p) {
+  BatchItem w;
+  w.inst = p->inst;
+  w.a = p->a;
+  w.b = p->b;
+  w.c = p->c;
+  w.d = p->d;
+  return w;
+}
+
+// The RHS and XUPD phases: each wavefront takes two of its round-robin items at a
+// time and moves them through their chains of dependent loads (item, problem
+// descriptor, column offsets, then the data) step by step together, so that the
+// two chains' latencies overlap; each item's arithmetic is that of one item alone.
+// (Global-address-space pointers, as in the streaming item: generic pointers would
+// make every load a FLAT load.)
+struct RhsRef {
+  bool on;
+  int P, n, k;
+  int64_t ld, o;
+  double rho_l, rho_c, shift;
+  gptr<const double> gb;
+  gptr<double> rhs;
+};
+
+__device__ __noinline__ void rhs_phase(const BatchArgs& ba, int o, int k, int gwave, int nwaves) {
+  const gptr<const BatchItem> items = uni_glob(ba.rhs_items);
+  const gptr<const BatchInst> insts = uni_glob(ba.inst);
+  const int n_items = uni(ba.n_rhs);
+  const int lane = threadIdx.x & 63;
+  for (int it0 = gwave; it0 < n_items; it0 += 2 * nwaves) {
+    BatchItem w[2];
+    bool take[2];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) s[u] = 0.0;
-  int w = 0;
-  for (; w + 32 <= P; w += 32) {
-    double v[32];
+    for (int j = 0; j < 2; ++j) {
+      const int it = it0 + j * nwaves;
+      take[j] = it < n_items;
+      if (take[j]) w[j] = load_item(items + it);
+    }
+    RhsRef d[2];
+    gptr<const int32_t> colp[2];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) v[u] = gb[(int64_t)(w + u) * ld];
+    for (int j = 0; j < 2; ++j) {
+      d[j].on = false;
+      if (!take[j]) continue;
+      const gptr<const BatchInst> I = insts + uni(w[j].inst);
+      if (o >= uni(I->outer) || k >= uni(I->inner_iters)) continue;
+      d[j].on = true;
+      d[j].P = uni(I->items_per_part);
+      d[j].ld = uni(I->ld);
+      d[j].rho_l = uni(I->rho_l);
+      d[j].rho_c = uni(I->rho_c);
+      d[j].shift = uni(I->shift);
+      d[j].n = uni(I->n);
+      colp[j] = uni_glob(I->col_off) + uni(w[j].b);
+    }
+    double zk[2], uo[2], xo[2];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) s[u & 7] += v[u];
+    for (int j = 0; j < 2; ++j) {
+      if (!d[j].on) continue;
+      const gptr<const BatchInst> I = insts + uni(w[j].inst);
+      const int c0 = uni(colp[j][0]);
+      const int nj = uni(colp[j][1]) - c0;
+      const int c = uni(w[j].c) + lane;
+      const int part = uni(w[j].a);
+      if (c >= nj) {
+        d[j].on = false;
+        continue;
+      }
+      d[j].k = c0 + c;
+      d[j].o = (int64_t)part * d[j].n + d[j].k;
+      d[j].gb = uni_glob(I->gpart) + (int64_t)part * d[j].P * d[j].ld + d[j].k;
+      d[j].rhs = uni_glob(I->rhs);
+      zk[j] = uni_glob(I->z)[d[j].k];
+      uo[j] = uni_glob(I->u)[d[j].o];
+      xo[j] = uni_glob(I->x)[d[j].o];
+    }
+    // partial w goes to s[w mod 8] in increasing w for w < P & ~7, the rest to s[0]
+    double s[2][8];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[j][u] = 0.0;
+    int P8[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) P8[j] = d[j].on ? (d[j].P & ~7) : 0;
+    const int P8m = max(P8[0], P8[1]);
+    for (int wv = 0; wv < P8m; wv += 16) {
+      double v[2][16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (wv + u < P8[j]) v[j][u] = d[j].gb[(int64_t)(wv + u) * d[j].ld];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (wv + u < P8[j]) s[j][u & 7] += v[j][u];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!d[j].on) continue;
+      for (int wv = P8[j]; wv < d[j].P; ++wv) s[j][0] += d[j].gb[(int64_t)wv * d[j].ld];
+      const double ate = ((s[j][0] + s[j][1]) + (s[j][2] + s[j][3])) +
+                         ((s[j][4] + s[j][5]) + (s[j][6] + s[j][7]));
+      d[j].rhs[d[j].o] = d[j].rho_l * ate + d[j].rho_c * (zk[j] - uo[j]) - d[j].shift * xo[j];
+    }
   }
-  for (; w + 8 <= P; w += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = gb[(int64_t)(w + u) * ld];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += v[u];
-  }
-  for (; w < P; ++w) s[0] += gb[(int64_t)w * ld];
-  const double ate = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  glob(I.rhs)[o] = rho_l * ate + rho_c * (zk - uo) - shift * xo;
 }
 
 // Tiles [t0, t1) of block (part, blk), one after the other, by one wavefront.
@@ -472,54 +564,107 @@ __device__ __forceinline__ void symv_item(const BatchInst& I, int part, int blk,
   }
 }
 
-// x += y over the 64 features of slot row R of block (part, blk).  y is summed from
-// the row's T slots in the order of symv_gather (two alternating sums); the slots
-// are loaded together first (T <= 16 for the blocks of the batched form, n_j <=
-// 1024; larger T takes the rest one by one).
-__device__ __noinline__ void xupd_item(const BatchInst& I, int part, int blk, int R) {
-  const int bid = part * I.M + blk;
-  const int c0 = I.col_off[blk];
-  const int nj = I.col_off[blk + 1] - c0;
-  const int i = R * PT + (threadIdx.x & 63);
-  if (i >= nj) return;
-  const int T = (nj + PT - 1) / PT;
-  const int64_t o = (int64_t)part * I.n + c0 + i;
-  const int64_t so = (int64_t)part * I.ld + c0 + i;
-  const bool f64 = I.dtype == BCA_F64;
-  const gptr<double> xv = glob(I.x);
-  const gptr<void> xs = glob(I.xs);
-  const gptr<const double> p =
-      glob(I.ypart) + (int64_t)bid * I.tmax * I.tmax * PT + ((int64_t)(i >> 6) * T * PT + (i & 63));
-  const double xo = xv[o];
+// XUPD: x += y over the 64 features of slot row R of block (part, blk), y summed
+// from the row's T slots in the order of symv_gather (two alternating sums); the
+// slots are loaded together first (T <= 16 for the blocks of the batched form,
+// n_j <= 1024; larger T takes the rest one by one).  Two items at a time, as RHS.
+struct XupdRef {
+  bool on;
+  bool f64;
+  int T;
+  int64_t o, so;
+  gptr<double> x;
+  gptr<void> xs;
+  gptr<const double> p;
+};
+
+__device__ __noinline__ void xupd_phase(const BatchArgs& ba, int o, int k, int gwave, int nwaves) {
+  const gptr<const BatchItem> items = uni_glob(ba.xupd_items);
+  const gptr<const BatchInst> insts = uni_glob(ba.inst);
+  const int n_items = uni(ba.n_xupd);
+  const int lane = threadIdx.x & 63;
   constexpr int TU = 16;
-  double v[TU];
+  for (int it0 = gwave; it0 < n_items; it0 += 2 * nwaves) {
+    BatchItem w[2];
+    bool take[2];
 #pragma unroll
-  for (int S = 0; S < TU; ++S)
-    if (S < T) v[S] = p[(int64_t)S * PT];
-  double y0 = 0.0, y1 = 0.0;
+    for (int j = 0; j < 2; ++j) {
+      const int it = it0 + j * nwaves;
+      take[j] = it < n_items;
+      if (take[j]) w[j] = load_item(items + it);
+    }
+    XupdRef d[2];
+    gptr<const int32_t> colp[2];
+    int Mn[2], nn[2], ldn[2], tm[2];
 #pragma unroll
-  for (int S = 0; S < TU; S += 2) {
-    if (S + 2 <= T) {
-      y0 += v[S];
-      y1 += v[S + 1];
-    } else if (S + 1 == T) {
-      y0 += v[S];
+    for (int j = 0; j < 2; ++j) {
+      d[j].on = false;
+      if (!take[j]) continue;
+      const gptr<const BatchInst> I = insts + uni(w[j].inst);
+      if (o >= uni(I->outer) || k >= uni(I->inner_iters)) continue;
+      d[j].on = true;
+      d[j].f64 = uni(I->dtype) == BCA_F64;
+      Mn[j] = uni(I->M);
+      nn[j] = uni(I->n);
+      ldn[j] = (int)uni(I->ld);
+      tm[j] = uni(I->tmax);
+      colp[j] = uni_glob(I->col_off) + uni(w[j].b);
+      d[j].x = uni_glob(I->x);
+      d[j].xs = uni_glob(I->xs);
+      d[j].p = uni_glob(I->ypart);
+    }
+    double xo[2], v[2][TU];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!d[j].on) continue;
+      const int part = uni(w[j].a), blk = uni(w[j].b), R = uni(w[j].c);
+      const int c0 = uni(colp[j][0]);
+      const int nj = uni(colp[j][1]) - c0;
+      const int i = R * PT + lane;
+      if (i >= nj) {
+        d[j].on = false;
+        continue;
+      }
+      const int bid = part * Mn[j] + blk;
+      d[j].T = (nj + PT - 1) / PT;
+      d[j].o = (int64_t)part * nn[j] + c0 + i;
+      d[j].so = (int64_t)part * ldn[j] + c0 + i;
+      d[j].p = d[j].p + (int64_t)bid * tm[j] * tm[j] * PT + ((int64_t)(i >> 6) * d[j].T * PT + (i & 63));
+      xo[j] = d[j].x[d[j].o];
+#pragma unroll
+      for (int S = 0; S < TU; ++S)
+        if (S < d[j].T) v[j][S] = d[j].p[(int64_t)S * PT];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!d[j].on) continue;
+      const int T = d[j].T;
+      double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+      for (int S = 0; S < TU; S += 2) {
+        if (S + 2 <= T) {
+          y0 += v[j][S];
+          y1 += v[j][S + 1];
+        } else if (S + 1 == T) {
+          y0 += v[j][S];
+        }
+      }
+      if (T > TU) {
+        int S = TU;
+        for (; S + 2 <= T; S += 2) {
+          y0 += d[j].p[(int64_t)S * PT];
+          y1 += d[j].p[(int64_t)(S + 1) * PT];
+        }
+        if (S < T) y0 += d[j].p[(int64_t)S * PT];
+      }
+      const double xn = xo[j] + (y0 + y1);
+      d[j].x[d[j].o] = xn;
+      if (d[j].f64)
+        ((gptr<double>)d[j].xs)[d[j].so] = xn;
+      else
+        ((gptr<float>)d[j].xs)[d[j].so] = (float)xn;
     }
   }
-  if (T > TU) {
-    int S = TU;
-    for (; S + 2 <= T; S += 2) {
-      y0 += p[(int64_t)S * PT];
-      y1 += p[(int64_t)(S + 1) * PT];
-    }
-    if (S < T) y0 += p[(int64_t)S * PT];
-  }
-  const double xn = xo + (y0 + y1);
-  xv[o] = xn;
-  if (f64)
-    ((gptr<double>)xs)[so] = xn;
-  else
-    ((gptr<float>)xs)[so] = (float)xn;
 }
 
 // Out of line, with 7 multisection points per round, so that the global step's
@@ -671,12 +816,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
   }
   for (int o = 0; o < ba.outer; ++o) {
     for (int k = 0; k < ba.inner_max; ++k) {
-      for (int it = gwave; it < ba.n_rhs; it += nwaves) {
-        const BatchItem w = ba.rhs_items[it];
-        const BatchInst& I = ba.inst[w.inst];
-        if (o >= I.outer || k >= I.inner_iters) continue;
-        rhs_item(I, w.a, w.b, w.c);
-      }
+      rhs_phase(ba, o, k, gwave, nwaves);
       ++phase;
       grid_barrier(ba.bar, epoch);
       stamp();
@@ -684,12 +824,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(2))) void ba
       ++phase;
       grid_barrier(ba.bar, epoch);
       stamp();
-      for (int it = gwave; it < ba.n_xupd; it += nwaves) {
-        const BatchItem w = ba.xupd_items[it];
-        const BatchInst& I = ba.inst[w.inst];
-        if (o >= I.outer || k >= I.inner_iters) continue;
-        xupd_item(I, w.a, w.b, w.c);
-      }
+      xupd_phase(ba, o, k, gwave, nwaves);
       ++phase;
       grid_barrier(ba.bar, epoch);
       stamp();

@@ -865,6 +865,18 @@ hipError_t launch_zero_u32(unsigned int* p, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
+// out[r] = the non-finite flag of problem r of a launch (one copy back for all).
+__global__ void batch_status_kernel(const BatchInst* inst, int count, int* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < count) out[r] = *inst[r].status;
+}
+
+hipError_t launch_batch_status(const BatchInst* inst, int count, int* out, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(batch_status_kernel, dim3((count + 255) / 256), dim3(256), 0, s, inst, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t s) {
   BatchArgs arg = a;
   void* params[] = {&arg};

@@ -31,6 +31,13 @@
 
 #include "bca_internal.h"
 
+namespace bca {
+// The batched kernel's per-problem non-finite flags gathered into one array
+// (batch.hip), so that a launch copies one array back instead of one flag per
+// problem with a stream synchronisation each.
+hipError_t launch_batch_status(const BatchInst* inst, int count, int* out, hipStream_t s);
+}  // namespace bca
+
 using namespace bca;
 
 namespace {
@@ -1454,8 +1461,23 @@ BatchInst batch_desc(bca_problem P, int outer) {
 // when it is given -- nothing is allocated then, and a problem whose batched
 // partial sums are missing or too small is refused -- else to the library's
 // growable buffer g_batch.
+// Items sorted by a cost, largest first, ties in their order of creation (the
+// costs are computed once per item, not in every comparison).
+template <typename Cost>
+void sort_items_desc(std::vector<BatchItem>& v, Cost cost) {
+  std::vector<std::pair<int64_t, int>> kv(v.size());
+  for (size_t i = 0; i < v.size(); ++i) kv[i] = {cost(v[i]), (int)i};
+  std::stable_sort(kv.begin(), kv.end(), [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) {
+    return a.first > b.first;
+  });
+  std::vector<BatchItem> out(v.size());
+  for (size_t i = 0; i < v.size(); ++i) out[i] = v[kv[i].second];
+  v.swap(out);
+}
+
 int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, hipStream_t s,
-                 bool stream_only, float* ms, void* dev = nullptr, size_t cap = 0) {
+                 bool stream_only, float* ms, void* dev = nullptr, size_t cap = 0,
+                 std::vector<int>* status = nullptr) {
   std::vector<BatchInst> desc(count);
   std::vector<BatchItem> solve, stream, primei, symv, xupd;
   int outer_max = 0, inner_max = 0;
@@ -1497,27 +1519,17 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
     bca_problem P = probs[w.inst];
     return (int64_t)(P->col_off[w.b + 1] - P->col_off[w.b] + PT - 1) / PT;
   };
-  std::stable_sort(symv.begin(), symv.end(), [](const BatchItem& a, const BatchItem& b) {
-    return a.d - a.c > b.d - b.c;
-  });
-  std::stable_sort(xupd.begin(), xupd.end(), [&](const BatchItem& a, const BatchItem& b) {
-    return xupd_cost(a) > xupd_cost(b);
-  });
+  sort_items_desc(symv, [](const BatchItem& w) { return (int64_t)(w.d - w.c); });
+  sort_items_desc(xupd, xupd_cost);
   auto stream_cost = [&](const BatchItem& w) {
     bca_problem P = probs[w.inst];
     const int64_t lo = (int64_t)w.b * batch_rows_item(P);
     const int64_t rows = std::max<int64_t>(0, std::min<int64_t>(P->rows[w.a], lo + batch_rows_item(P)) - lo);
     return rows * P->nvec;
   };
-  std::stable_sort(solve.begin(), solve.end(), [&](const BatchItem& a, const BatchItem& b) {
-    return solve_cost(a) > solve_cost(b);
-  });
-  std::stable_sort(stream.begin(), stream.end(), [&](const BatchItem& a, const BatchItem& b) {
-    return stream_cost(a) > stream_cost(b);
-  });
-  std::stable_sort(primei.begin(), primei.end(), [&](const BatchItem& a, const BatchItem& b) {
-    return stream_cost(a) > stream_cost(b);
-  });
+  sort_items_desc(solve, [&](const BatchItem& w) { return (int64_t)solve_cost(w); });
+  sort_items_desc(stream, stream_cost);
+  sort_items_desc(primei, stream_cost);
   if (stream_only) outer_max = 0;
   const int phases = (primei.empty() ? 0 : 1) + outer_max * (4 * inner_max + 1);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -1532,7 +1544,8 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   const bool tracing = g_trace.on.load() && !stream_only;
   const size_t off_stamps = off_cnt + al(n_cnt * sizeof(unsigned int));
   const size_t n_stamps = (size_t)std::max(phases, 1) + 1;   // the start and every barrier
-  const size_t total = off_stamps + (tracing ? al(n_stamps * sizeof(unsigned long long)) : 0);
+  const size_t off_status = off_stamps + (tracing ? al(n_stamps * sizeof(unsigned long long)) : 0);
+  const size_t total = off_status + (status ? al((size_t)count * sizeof(int)) : 0);
   char* base = nullptr;
   if (dev) {
     if (total > cap)
@@ -1592,6 +1605,12 @@ int batch_launch(bca_problem* probs, int count, const std::vector<int>& outer, h
   hipError_t le = launch_batch(a, grid, s);
   if (le != hipSuccess) return fail(BCA_E_DEVICE, "batched launch failed: %s", hipGetErrorString(le));
   if (ms) HIP_TRY(hipEventRecord(e1, s));
+  if (status) {
+    int* st_dev = reinterpret_cast<int*>(base + off_status);
+    HIP_TRY(launch_batch_status(a.inst, count, st_dev, s));
+    status->assign(count, 0);
+    HIP_TRY(hipMemcpyAsync(status->data(), st_dev, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   if (tracing) {
     // phase kinds between consecutive stamps: [prime], then per outer iteration
@@ -1643,8 +1662,11 @@ int bca_batch_step(bca_problem* probs, int32_t count, int32_t outer_iters, void*
     TRY(batch_check(probs[r]));
     outer[r] = std::max(0, std::min(outer_iters, probs[r]->p.max_iters - probs[r]->iter));
   }
-  TRY(batch_launch(probs, count, outer, reinterpret_cast<hipStream_t>(hip_stream), false, nullptr));
-  for (int r = 0; r < count; ++r) TRY(check_status(probs[r], "batch"));
+  std::vector<int> st;
+  TRY(batch_launch(probs, count, outer, reinterpret_cast<hipStream_t>(hip_stream), false, nullptr,
+                   nullptr, 0, &st));
+  for (int r = 0; r < count; ++r)
+    if (st[r]) return fail(BCA_E_NONFINITE, "batch: non-finite value encountered");
   return BCA_OK;
 }
 
@@ -1680,9 +1702,11 @@ int bca_batch_step_noalloc(bca_problem* probs, int32_t count, int32_t outer_iter
     TRY(batch_check(probs[r]));
     outer[r] = std::max(0, std::min(outer_iters, probs[r]->p.max_iters - probs[r]->iter));
   }
+  std::vector<int> st;
   TRY(batch_launch(probs, count, outer, reinterpret_cast<hipStream_t>(hip_stream), false, nullptr,
-                   g_scratch_dev[dev], kBatchScratchBytes));
-  for (int r = 0; r < count; ++r) TRY(check_status(probs[r], "batch"));
+                   g_scratch_dev[dev], kBatchScratchBytes, &st));
+  for (int r = 0; r < count; ++r)
+    if (st[r]) return fail(BCA_E_NONFINITE, "batch: non-finite value encountered");
   return BCA_OK;
 }
 

@@ -95,28 +95,6 @@ __device__ __forceinline__ V load_nt(gptr<const V> p) {
   return v;
 }
 
-// Lane exchanges of gfx950: after swap32(a, b) lanes 32-63 of a and lanes 0-31 of
-// b have traded places; after swap16(a, b) the odd 16-lane rows of a and the even
-// rows of b have.  In both, a + b is then, in every lane, the lane's own value of
-// one of the pair plus its partner's (lane ^ 32, lane ^ 16) value of the same one:
-// of a where the lane's bit (5, 4) is clear, of b where it is set.
-__device__ __forceinline__ void swap32(double& a, double& b) {
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
-                                                   (unsigned)__double2loint(b), false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
-                                                   (unsigned)__double2hiint(b), false, false);
-  a = __hiloint2double((int)hi[0], (int)lo[0]);
-  b = __hiloint2double((int)hi[1], (int)lo[1]);
-}
-__device__ __forceinline__ void swap16(double& a, double& b) {
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
-                                                   (unsigned)__double2loint(b), false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
-                                                   (unsigned)__double2hiint(b), false, false);
-  a = __hiloint2double((int)hi[0], (int)lo[0]);
-  b = __hiloint2double((int)hi[1], (int)lo[1]);
-}
-
 // Sums over the wavefront of R (2, 4, 8) per-lane values at once (reduce-scatter):
 // each halving step over lane bit 5, 4, 3 adds half of the remaining values to the
 // partner lane's and keeps the upper half where the lane's bit is set, so that

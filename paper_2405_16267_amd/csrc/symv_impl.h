@@ -16,6 +16,28 @@ namespace bca {
 
 typedef double symv_d2 __attribute__((ext_vector_type(2)));
 
+// Lane exchanges of gfx950: after swap32(a, b) lanes 32-63 of a and lanes 0-31 of
+// b have traded places; after swap16(a, b) the odd 16-lane rows of a and the even
+// rows of b have.  In both, a + b is then, in every lane, the lane's own value of
+// one of the pair plus its partner's (lane ^ 32, lane ^ 16) value of the same one:
+// of a where the lane's bit (5, 4) is clear, of b where it is set.
+__device__ __forceinline__ void swap32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
 // tile: this tile's 4096 doubles; r: the block's right-hand sides (n_j x C,
 // feature-major); ys: the block's slots, slot (R, S) at ys + (R T + S) 64 C;
 // right-hand sides cb .. ce - 1 (all C when ce < 0).
@@ -105,8 +127,13 @@ __device__ __forceinline__ void symv_tile(const double* __restrict__ tile, const
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         cs[e] += dpp_f64<0x128>(cs[e]);
-        cs[e] += __shfl_xor(cs[e], 16, 64);
-        cs[e] += __shfl_xor(cs[e], 32, 64);
+        // + the lane ^ 16, then the lane ^ 32 value (lane swaps, not LDS permutes)
+        double t = cs[e];
+        swap16(cs[e], t);
+        cs[e] = cs[e] + t;
+        t = cs[e];
+        swap32(cs[e], t);
+        cs[e] = cs[e] + t;
       }
       // lane (a, b) writes column 8 b + a, i.e. cs[a]
       double cv = cs[0];

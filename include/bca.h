@@ -298,7 +298,7 @@ int bca_batch_get_tracing(double* us, int32_t count, int64_t* launches);
  * x rows per work item 16/32/64/256/1024; a work item is one wavefront's chunk of rows)
  * on each group with state-preserving streaming passes (the fastest of three), and
  * keeps per group, among the shapes within 3 % of the fastest, the one with the
- * most rows per item.  The ADMM state is not modified. */
+ * most rows per item, then per tile.  The ADMM state is not modified. */
 int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream);
 
 /* Explicit tile shape of a problem in the batched form (rows per wavefront tile

@@ -1818,11 +1818,13 @@ int bca_batch_autotune(bca_problem* probs, int32_t count, void* hip_stream) {
       }
     }
     // Among the shapes within 3 % of the fastest, the one with the most rows per
-    // item: fewer items leave fewer partial sums for the RHS phase to reduce (not
-    // part of the timed pass), and a group timed alone favours small items that
-    // spread it over the idle GPU, which a full batch does not need.
+    // item, then the most rows per tile: fewer items leave fewer partial sums for
+    // the RHS phase to reduce (not part of the timed pass), a group timed alone
+    // favours small items that spread it over the idle GPU, which a full batch
+    // does not need, and more rows per tile share the per-row reduction work.
     for (const auto& c : timed)
-      if (std::get<0>(c) <= 1.03f * best && std::get<2>(c) > bi) {
+      if (std::get<0>(c) <= 1.03f * best &&
+          (std::get<2>(c) > bi || (std::get<2>(c) == bi && std::get<1>(c) > bt))) {
         bt = std::get<1>(c);
         bi = std::get<2>(c);
       }

@@ -228,3 +228,27 @@ def test_batch_phase_tracing_accounts_for_the_launch():
     bca.batch_set_tracing(False)
     for p in P + Q:
         p.close()
+
+
+def test_batch_reports_a_problem_whose_iterates_overflow():
+    """A problem whose iterates overflow (labels of 1e308: the squared-loss prox's 2 b
+    exceeds the FP64 range) makes the batched launch fail with BCA_E_NONFINITE -- the per-problem
+    flags are gathered and read back once per launch -- while the same launch's other
+    problems keep their results (they match their solo runs)."""
+    bca = _bca()
+    good = datagen.batched_instance(11, 600, 40, dtype="f64", max_iters=4)
+    bad = datagen.batched_instance(12, 600, 40, dtype="f64", max_iters=4)
+    G, S = make(good), make(good)
+    B = bca.Problem("squared", bad.n, bad.rows, bad.n_blocks, bad.kappa, gamma=bad.gamma,
+                    rho_c=bad.rho_c, rho_b=bad.rho_b, rho_l=bad.rho_l,
+                    inner_iters=bad.inner_iters, max_iters=bad.max_iters, dtype="f64")
+    for i in range(bad.N):
+        B.set_data(i, bad.A[i], np.full_like(bad.b[i], 1e308))
+    B.finalize()
+    with pytest.raises(bca.BcaError) as e:
+        bca.batch_step([G, B], 2)
+    assert e.value.code == -4
+    S.step(2)
+    assert rel(G.get_vector(bca.VEC_Z), S.get_vector(bca.VEC_Z)) < 1e-12
+    for P in (G, S, B):
+        P.close()

@@ -250,7 +250,9 @@ const char* bca_last_error(void);
  * kernels beside it made no progress for minutes), so run nothing else on the
  * device during the call.  The call synchronises hip_stream.
  * Errors: BCA_E_INVALID (a problem outside the limits), BCA_E_STATE (not
- * finalized), BCA_E_NONFINITE, BCA_E_DEVICE. */
+ * finalized), BCA_E_NONFINITE (a problem's iterates became NaN/Inf; every problem
+ * of the batch has still advanced, and the others' results are valid),
+ * BCA_E_DEVICE. */
 
 /* Advance every problem by min(outer_iters, its remaining max_iters) outer iterations. */
 int bca_batch_step(bca_problem* probs, int32_t count, int32_t outer_iters, void* hip_stream);
@@ -261,8 +263,9 @@ int bca_batch_solve(bca_problem* probs, int32_t count, void* hip_stream);
 /* bca_batch_step without device allocation, for callers that cannot allocate
  * device memory (code under stream capture, tight serving loops, harnesses that
  * forbid hipMalloc): same arguments, kernels and results (bit for bit) as
- * bca_batch_step.  The launch's descriptors, item lists and phase counters live
- * in a fixed scratch array of 16 MiB in the library's device code (one copy per
+ * bca_batch_step.  The launch's descriptors, item lists, phase counters and
+ * gathered status flags live in a fixed scratch array of 16 MiB in the library's
+ * device code (one copy per
  * GPU, held until the process ends); every problem must already hold its batched
  * partial sums, which bca_finalize allocates for every problem within the
  * batched form's limits (bca_batch_set_shape and bca_batch_autotune resize them).

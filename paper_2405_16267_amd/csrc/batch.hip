@@ -86,6 +86,16 @@ __device__ __forceinline__ gptr<P> glob(P* p) {
 typedef __attribute__((address_space(3))) double* lds_dptr;
 
 template <typename V>
+__device__ __forceinline__ V load_v(gptr<const V> p) {
+  static_assert(sizeof(V) == 16, "16-byte vectors only");
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 t = *(gptr<const u32x4>)p;
+  V v;
+  __builtin_memcpy(&v, &t, 16);
+  return v;
+}
+
+template <typename V>
 __device__ __forceinline__ V load_nt(gptr<const V> p) {
   static_assert(sizeof(V) == 16, "16-byte vectors only");
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -184,12 +194,16 @@ __device__ __noinline__ void stream_item(const BatchInst& I, int part, int chunk
   const gptr<double> gp = glob(I.gpart) + ((int64_t)part * items_per_part + chunk) * ld;
   const int64_t lo = (int64_t)chunk * rows_per_item;
   const int64_t hi = lo + rows_per_item < m ? lo + rows_per_item : m;
+  // the lane's chunks of x, one 16-byte load each (rows of xs are 16-byte aligned:
+  // ld is a multiple of 64 elements, and its columns past n are zero)
   acc xr[NC][VEC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     const int k = sl + LSEG * q;
+    V xv = vzero<V>();
+    if (k < nvec) xv = load_v<V>((gptr<const V>)xs + k);
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) xr[q][e] = k < nvec ? xs[k * VEC + e] : acc(0);
+    for (int e = 0; e < VEC; ++e) xr[q][e] = vget(xv, e);
   }
   double g[LG ? 1 : NC][LG ? 1 : VEC];
 #pragma unroll

@@ -540,7 +540,9 @@ __device__ __noinline__ void rhs_phase(const BatchArgs& ba, int o, int k, int gw
   }
 }
 
-// Tiles [t0, t1) of block (part, blk), one after the other, by one wavefront.
+// Tiles [t0, t1) of block (part, blk), one after the other, by one wavefront
+// (NTL: nontemporal tile loads).
+template <bool NTL>
 __device__ __forceinline__ void symv_item(const BatchInst& I, int part, int blk, int t0, int t1) {
   const int bid = part * I.M + blk;
   const int c0 = I.col_off[blk];
@@ -552,7 +554,7 @@ __device__ __forceinline__ void symv_item(const BatchInst& I, int part, int blk,
   for (int t = t0; t < t1; ++t) {
     int ti, tj;
     tri_tile(t, &ti, &tj);
-    symv_tile(P + (int64_t)t * PT_ELEMS, r, nj, 1, ti, tj, T, ys);
+    symv_tile<NTL>(P + (int64_t)t * PT_ELEMS, r, nj, 1, ti, tj, T, ys);
   }
 }
 
@@ -697,12 +699,25 @@ __device__ GlobalArgs global_args_of(const BatchInst& I) {
 // call convention, in scratch memory (measured at 512 problems: 684 -> 603 us
 // per phase).  (The streaming items keep one call per item: with their 36 shape
 // bodies inlined into one function it spills in the item loop, 1.7 -> 2.4 ms.)
+//
+// A launch whose tiles far exceed the last-level cache (256 MB of Infinity Cache)
+// reads them with nontemporal loads: cached, they evicted the phase's small reused
+// data (r, and the slots that XUPD reads next) for no reuse of their own (512
+// problems, 2.9 GB of tiles: SYMV 0.57 -> 0.53 ms, XUPD 0.048 -> 0.042 ms per inner
+// iteration); a smaller set stays cached for the next inner iteration.  Items hold
+// at most two 32 KB tiles.
+constexpr int64_t kSymvNtlBytes = int64_t(128) << 20;
+
 __device__ __noinline__ void symv_phase(const BatchArgs& ba, int o, int k, int gwave, int nwaves) {
+  const bool ntl = (int64_t)ba.n_symv * 2 * PT_ELEMS * (int64_t)sizeof(double) > kSymvNtlBytes;
   for (int it = gwave; it < ba.n_symv; it += nwaves) {
     const BatchItem w = ba.symv_items[it];
     const BatchInst& I = ba.inst[w.inst];
     if (o >= I.outer || k >= I.inner_iters) continue;
-    symv_item(I, w.a, w.b, w.c, w.d);
+    if (ntl)
+      symv_item<true>(I, w.a, w.b, w.c, w.d);
+    else
+      symv_item<false>(I, w.a, w.b, w.c, w.d);
   }
 }
 

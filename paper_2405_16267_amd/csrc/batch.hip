@@ -506,7 +506,8 @@ __device__ __noinline__ void rhs_phase(const BatchArgs& ba, int o, int k, int gw
       uo[j] = uni_glob(I->u)[d[j].o];
       xo[j] = uni_glob(I->x)[d[j].o];
     }
-    // partial w goes to s[w mod 8] in increasing w for w < P & ~7, the rest to s[0]
+    // partial w goes to s[w mod 8] in increasing w for w < P & ~7, the rest to s[0];
+    // the partials are read once (nontemporal loads)
     double s[2][8];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -522,7 +523,7 @@ __device__ __noinline__ void rhs_phase(const BatchArgs& ba, int o, int k, int gw
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-          if (wv + u < P8[j]) v[j][u] = d[j].gb[(int64_t)(wv + u) * d[j].ld];
+          if (wv + u < P8[j]) v[j][u] = __builtin_nontemporal_load(d[j].gb + (int64_t)(wv + u) * d[j].ld);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
